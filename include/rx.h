@@ -1,0 +1,226 @@
+/*
+ * rx.h -- C ABI of the MI355X streaming global-RX anomaly scorer.
+ *
+ * What is computed (paper: Section "System Implementation / Detection
+ * Algorithm", Eq. 1): every band is a variable and every pixel a sample; the
+ * band mean mu and the B x B covariance Sigma are taken over all pixels of
+ * the statistics window (pixels being scored included), and each pixel
+ * spectrum s scores
+ *       delta = (s - mu)^T Sigma^{-1} (s - mu)
+ * (squared Mahalanobis distance).  A threshold marks pixels above a
+ * configurable value (same section; the flights use 0.110 of the per-set
+ * maximum).  Lines arrive from a push-broom sensor (Section "System
+ * Architecture / Data Acquisition"); they are pushed in blocks.  Each block
+ * first joins the statistics window and is then scored with the updated
+ * statistics (the line-based form the paper proposes in Section
+ * "Discussion / Performance"; one block = one 1000-line cube with a
+ * 1000-line window reproduces the paper's per-cube detector).
+ *
+ * Numerics: the statistics are a streaming merge of per-block centred
+ * scatter matrices (covariance product on matrix cores in the configured
+ * precision, FP32 centring, FP64 merge); the optional ridge, equilibration,
+ * Cholesky factorisation and triangular inverse run in FP64 on the GPU;
+ * whitening y = W (x - mu) with W^T W = (Sigma + lambda I)^{-1} runs on
+ * matrix cores in the configured precision with FP32 accumulation (FP64 on
+ * the plain FP64 path), and delta = |y|^2.
+ *
+ * Conventions for every entry point:
+ *  - Returns rx_status; nothing throws, aborts or exits.  On a non-OK status
+ *    rx_last_error() returns a thread-local message describing it.
+ *  - The caller owns every buffer it passes; the library never frees them.
+ *    The library owns all device state behind an rx_stream / rx_server and
+ *    frees it in rx_destroy / rx_server_destroy.
+ *  - Calls on one rx_stream must be serialised by the caller; different
+ *    streams may be driven from different threads.
+ *  - hip_stream arguments are hipStream_t values passed as void* (NULL = the
+ *    null stream).  The library orders its work after everything already
+ *    enqueued on hip_stream and, for device outputs, makes hip_stream wait
+ *    for the result; it never blocks the host except where stated.
+ */
+#ifndef RX_H_
+#define RX_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rx_stream rx_stream;   /* one sensor stream; opaque, library-owned */
+typedef struct rx_server rx_server;   /* many streams sharing one GPU; opaque */
+
+typedef enum {
+  RX_OK = 0,
+  RX_E_ARG = -1,       /* bad size, enum, null pointer or struct_size */
+  RX_E_NOMEM = -2,     /* device or pinned-host allocation failed */
+  RX_E_NOTREADY = -3,  /* window holds N <= B pixels and no ridge: Sigma is singular; scores NaN */
+  RX_E_SINGULAR = -4,  /* non-positive pivot in the FP64 Cholesky; that block's scores are NaN */
+  RX_E_DEVICE = -5,    /* a HIP runtime call failed */
+  RX_E_BUDGET = -6,    /* server: admission refused by the HBM budget or stream-slot limit */
+  RX_E_STATE = -7      /* call on a destroyed object or in the wrong order */
+} rx_status;
+
+typedef enum { RX_IN_U16 = 0, RX_IN_F32 = 1, RX_IN_F64 = 2 } rx_in_type;
+typedef enum { RX_BIL = 0 /* band-interleaved by line: [line][band][sample] */ } rx_layout;
+typedef enum { RX_FP64 = 0, RX_FP32 = 1, RX_BF16 = 2, RX_FP16 = 3, RX_FP8_E4M3 = 4 } rx_prec;
+typedef enum { RX_THR_ABS = 0, RX_THR_REL_MAX = 1, RX_THR_TOPK = 2 } rx_thr_mode;
+
+#define RX_MAX_BANDS 320
+
+typedef struct rx_config {
+  uint32_t struct_size;   /* must be sizeof(rx_config) (ABI versioning) */
+  int32_t bands;          /* B, 1 .. RX_MAX_BANDS */
+  int32_t samples;        /* S >= 1 samples (pixels) per line */
+  int32_t in_type;        /* rx_in_type of the pushed values */
+  int32_t bit_depth;      /* u16 input: values must be < 2^bit_depth (informational), 0 = 16 */
+  int32_t layout;         /* rx_layout; only RX_BIL */
+  int32_t syrk_prec;      /* covariance-product precision: FP64, FP32, BF16 or FP16 */
+  int32_t whiten_prec;    /* whitening precision: FP64, FP32, BF16, FP16 or FP8_E4M3 */
+  int32_t ddof;           /* covariance normaliser 1/(N - ddof); 0 (default) or 1 */
+  int32_t block_lines;    /* 0: each push is one block; >0: pushes are cut into blocks of at
+                             most this many lines (the last block of a push may be shorter) */
+  int64_t window_lines;   /* 0: cumulative window; R > 0: statistics restart every R lines
+                             (blocks never straddle a window edge; 1000 = the paper's cube) */
+  double ridge_rel;       /* rho >= 0: lambda = rho * trace(Sigma) / B is added to the diagonal */
+  int32_t device;         /* HIP device ordinal */
+  int32_t flags;          /* reserved, must be 0 */
+} rx_config;
+
+typedef struct rx_counters {
+  int64_t lines_pushed;     /* lines accepted so far */
+  int64_t blocks;           /* blocks processed */
+  int64_t singular_blocks;  /* blocks whose factorisation hit a non-positive pivot */
+  int64_t notready_blocks;  /* blocks scored while N <= B without a ridge */
+  int64_t pending_px;       /* scores produced and not yet consumed by rx_scores */
+  int64_t window_px;        /* N, pixels in the current statistics window */
+} rx_counters;
+
+/* Fill *cfg with defaults for B bands and S samples: u16 input, 12-bit,
+ * BIL, BF16 covariance and whitening, ddof 0, one block per push,
+ * cumulative window, no ridge, device 0.  RX_E_ARG on a null cfg. */
+rx_status rx_config_init(rx_config* cfg, int32_t bands, int32_t samples);
+
+/* Create a stream.  server may be NULL (stand-alone stream); otherwise the
+ * stream is admitted by the server's HBM budget (RX_E_BUDGET if it does not
+ * fit or every slot is taken).  Allocates the stream's resident state
+ * (window mean and scatter matrix in FP64) on cfg->device.  *out receives
+ * the handle (NULL on failure). */
+rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
+
+/* Push n_lines >= 1 lines, BIL [n_lines][B][S] of cfg->in_type, contiguous.
+ * is_device_ptr = 0: lines is host memory, copied before the call returns
+ * (the caller may reuse it at once).  is_device_ptr = 1: lines is device
+ * memory on cfg->device; it is read asynchronously and must stay unchanged
+ * until rx_sync returns or hip_stream passes an rx_wait on this stream.
+ * The lines are cut into blocks (cfg->block_lines, window edges); each block
+ * updates the statistics and is then scored.  Scores join the stream's
+ * pending FIFO in pixel order (p = line * S + sample).  Asynchronous.
+ * RX_E_NOTREADY when a block is scored with N <= B and no ridge (its scores
+ * are NaN, the statistics are still updated). */
+rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_lines, int32_t is_device_ptr,
+                        void* hip_stream);
+
+/* Pop up to max_px of the oldest pending scores (FP32) into out.
+ * out_is_device = 0: host buffer, the call blocks until they are written.
+ * out_is_device = 1: device buffer on cfg->device, written asynchronously
+ * and ordered before later work on hip_stream.  *n_written = count popped. */
+rx_status rx_scores(rx_stream* s, float* out, int64_t max_px, int64_t* n_written,
+                    int32_t out_is_device, void* hip_stream);
+
+/* As rx_scores but FP64; on the plain FP64 path (whiten_prec = RX_FP64) these
+ * are the FP64 scores, otherwise the FP32 scores widened. */
+rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_written,
+                        int32_t out_is_device, void* hip_stream);
+
+/* Threshold mask over all pending scores, without consuming them.
+ * mode RX_THR_ABS: delta > tau.  RX_THR_REL_MAX: delta > tau * max(pending)
+ * (the paper's normalised threshold, e.g. tau = 0.110).  RX_THR_TOPK: the k
+ * largest pending scores, ties to the lower pixel index.  NaN scores are
+ * never marked.  Bit j of byte q is pending pixel 8q + j; ceil(n/8) bytes are
+ * written (max_bytes must be at least that).  *n_px = pending pixels covered.
+ * out_is_device as in rx_scores. */
+rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits,
+                  int64_t max_bytes, int64_t* n_px, int32_t out_is_device, void* hip_stream);
+
+/* Make hip_stream wait for every block pushed so far (no host block). */
+rx_status rx_wait(rx_stream* s, void* hip_stream);
+
+/* Block the host until every block pushed so far is done.  Returns the
+ * first sticky error raised by the device since the previous rx_sync
+ * (RX_E_SINGULAR) and clears it. */
+rx_status rx_sync(rx_stream* s);
+
+/* Counters (blocks the host, like rx_sync, without clearing errors). */
+rx_status rx_get_counters(rx_stream* s, rx_counters* out);
+
+/* Destroy a stream: waits for its work, frees its device memory, and
+ * releases its server admission.  NULL is accepted (no-op). */
+rx_status rx_destroy(rx_stream* s);
+
+/* Thread-local message for the last non-OK status on this thread. */
+const char* rx_last_error(void);
+
+/* Checkpoint/restore hooks.  rx_get_stats blocks, then writes the window
+ * count, the mean [B] and the covariance M2/(N - ddof) [B][B] (row-major,
+ * full symmetric); mean and cov may be NULL.  rx_set_stats replaces the
+ * window with (n, mean, cov): the scatter matrix becomes cov * (n - ddof). */
+rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double* cov);
+rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, const double* cov);
+
+/* Phase timing for measurement: with enable = 1, every later push records a
+ * pair of HIP events on the stream the kernels run on around each phase
+ * (0 centring shift, 1 covariance product, 2 statistics merge, 3 FP64
+ * factorisation, 4 whitening + score).  rx_phase_times blocks, then writes the
+ * accumulated milliseconds ms[5] and launch counts launches[5] since the
+ * last rx_profile call (which also resets them). */
+rx_status rx_profile(rx_stream* s, int32_t enable);
+rx_status rx_phase_times(rx_stream* s, double* ms, int64_t* launches);
+
+/* Test hook: the FP64 whitening factor W (lower triangular, [B][B]
+ * row-major, W^T W = (Sigma + lambda I)^{-1}) of the most recent block. */
+rx_status rx_get_whitener(rx_stream* s, double* w);
+
+/* ---------------------------------------------------------------- serving
+ * A server admits many streams on one GPU under an HBM budget and runs their
+ * blocks together: rx_server_submit queues a block for a stream (device
+ * lines; the server copies nothing), rx_server_step launches every queued
+ * block of every stream in one batched pass (one launch per kernel and
+ * precision group), and completions are reported with their arrival stamps
+ * so latency can be measured.  A stream's result is the same alone and in
+ * any mix (bit-identical: no reduction depends on the batch composition). */
+rx_status rx_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32_t device,
+                           rx_server** out);
+rx_status rx_server_destroy(rx_server* srv);
+
+/* Bytes of device memory a stream with this config reserves when its blocks
+ * have at most max_block_lines lines (the admission charge; a served stream
+ * takes blocks of at most cfg->block_lines lines, 128 when that is 0). */
+rx_status rx_stream_footprint(const rx_config* cfg, int32_t max_block_lines, size_t* bytes);
+
+/* Queue one block of n_lines (<= the stream's block limit) device lines for
+ * a stream admitted on srv.  The lines must stay unchanged until the block
+ * is reported done by rx_server_poll.  tag is returned on completion.  A
+ * block must not straddle a window edge (RX_E_ARG at step time). */
+rx_status rx_server_submit(rx_server* srv, rx_stream* s, const void* lines_dev, int64_t n_lines, uint64_t tag);
+
+/* Launch the oldest queued block of every stream that has one, all in one
+ * batched pass (statistics, factorisations and whitening of every stream
+ * in shared launches).  Asynchronous; *n_blocks = blocks launched. */
+rx_status rx_server_step(rx_server* srv, int32_t* n_blocks);
+
+/* Report finished blocks in launch order: up to max_tags tags are written.
+ * block = 0 returns at once; block = 1 waits for every launched block. */
+rx_status rx_server_poll(rx_server* srv, uint64_t* tags, int32_t max_tags, int32_t* n_done, int32_t block);
+
+/* Wait for every launched block. */
+rx_status rx_server_sync(rx_server* srv);
+
+/* Queue depth, blocks in flight and admitted bytes (any pointer may be NULL). */
+rx_status rx_server_queued(rx_server* srv, int32_t* queued, int32_t* inflight, size_t* used_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RX_H_ */

@@ -1,0 +1,234 @@
+// Device-side building blocks shared by the RX kernels (gfx950 / CDNA4 only).
+//
+// Layout conventions
+//  * Input lines are BIL: x[line][band][sample]; pixel p = line * S + sample.
+//  * Bands are padded to Bp = 16 * ceil(B / 16) in every device matrix; the
+//    padding rows/columns hold zeros (identity on the diagonal of the
+//    equilibrated covariance) so every 16x16 matrix-core tile is whole.
+//  * Matrix-core tiles are 16 x 16 outputs (v_mfma_*_16x16x*): lane l owns
+//    four outputs of column l%16 -- rows 4*(l/16)+j (j = 0..3) for the FP32-
+//    accumulating formats, rows (l/16)+4*j for v_mfma_f64_16x16x4f64 (checked
+//    on gfx950 with a unique-value probe); operand lanes own row/column l%16
+//    and the k-group l/16 of KV consecutive k values.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rxk {
+
+enum InType { IN_U16 = 0, IN_F32 = 1, IN_F64 = 2 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3, P_FP8 = 4 };
+
+constexpr int TILE = 16;      // matrix-core output tile edge (bands)
+constexpr int SUP = 64;       // covariance super-tile edge owned by one workgroup
+constexpr int MAXT = 20;      // max 16-band tiles: B <= 320
+constexpr int KC = 64;        // pixels per chunk (one line segment)
+constexpr int MAXB = 8;       // batches per launch (kernel-argument descriptors)
+constexpr int NT = 256;       // threads per workgroup of the streaming kernels
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+// ------------------------------------------------------------------ per-precision traits
+// storage: element type kept in LDS / global for the operand;  frag: operand
+// register type;  acc: accumulator vector;  KV: k values per lane;  KK: k per
+// instruction.
+template <int P> struct MM;
+
+template <> struct MM<P_F64> {
+  using storage = double; using frag = double; using acc = f64x4; using accs = double;
+  static constexpr int KV = 1, KK = 4;
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int j) { return g + 4 * j; }
+};
+template <> struct MM<P_F32> {
+  using storage = float; using frag = float; using acc = f32x4; using accs = float;
+  static constexpr int KV = 1, KK = 4;
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int j) { return 4 * g + j; }
+};
+template <> struct MM<P_BF16> {
+  using storage = uint16_t; using frag = bf16x8; using acc = f32x4; using accs = float;
+  static constexpr int KV = 8, KK = 32;
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int j) { return 4 * g + j; }
+};
+template <> struct MM<P_F16> {
+  using storage = uint16_t; using frag = f16x8; using acc = f32x4; using accs = float;
+  static constexpr int KV = 8, KK = 32;
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int j) { return 4 * g + j; }
+};
+template <> struct MM<P_FP8> {
+  using storage = uint8_t; using frag = long; using acc = f32x4; using accs = float;
+  static constexpr int KV = 8, KK = 32;
+  static __device__ __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int g, int j) { return 4 * g + j; }
+};
+
+// ------------------------------------------------------------------ conversions (RNE)
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  __bf16 h = (__bf16)f;                       // round to nearest even
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;                   // round to nearest even
+  return __builtin_bit_cast(uint16_t, h);
+}
+// OCP FP8 E4M3 (bias 7, max finite 448, no infinities, 0x7F/0xFF are NaN):
+// round to nearest even; magnitudes above 448 saturate to 448; subnormals
+// (m * 2^-9) are kept.
+__device__ __forceinline__ uint8_t f32_to_e4m3(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  uint32_t sign = (u >> 24) & 0x80u;
+  float a = __builtin_fabsf(f);
+  if (!(a == a)) return (uint8_t)(sign | 0x7Fu);
+  if (a >= 448.0f) return (uint8_t)(sign | 0x7Eu);
+  if (a < 0.015625f) {                        // below 2^-6: subnormal grid of 2^-9
+    float m = __builtin_rintf(a * 512.0f);    // 0..8 (8 = smallest normal)
+    return (uint8_t)(sign | (uint32_t)m);
+  }
+  int e = (int)((__builtin_bit_cast(uint32_t, a) >> 23) & 0xff) - 127;   // -6..8
+  float scaled = __builtin_ldexpf(a, -e);     // [1, 2)
+  float m = __builtin_rintf((scaled - 1.0f) * 8.0f);
+  uint32_t mi = (uint32_t)m;
+  if (mi == 8u) { mi = 0; ++e; }
+  if (e > 8 || (e == 8 && mi == 7u)) return (uint8_t)(sign | 0x7Eu);
+  return (uint8_t)(sign | ((uint32_t)(e + 7) << 3) | mi);
+}
+
+template <int P> __device__ __forceinline__ typename MM<P>::storage to_storage(float v);
+template <> __device__ __forceinline__ float to_storage<P_F32>(float v) { return v; }
+template <> __device__ __forceinline__ uint16_t to_storage<P_BF16>(float v) { return f32_to_bf16_bits(v); }
+template <> __device__ __forceinline__ uint16_t to_storage<P_F16>(float v) { return f32_to_f16_bits(v); }
+template <> __device__ __forceinline__ uint8_t to_storage<P_FP8>(float v) { return f32_to_e4m3(v); }
+
+// Load one operand fragment: KV consecutive storage elements at p.
+template <int P> __device__ __forceinline__ typename MM<P>::frag load_frag(const typename MM<P>::storage* p);
+template <> __device__ __forceinline__ double load_frag<P_F64>(const double* p) { return *p; }
+template <> __device__ __forceinline__ float load_frag<P_F32>(const float* p) { return *p; }
+template <> __device__ __forceinline__ bf16x8 load_frag<P_BF16>(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+template <> __device__ __forceinline__ f16x8 load_frag<P_F16>(const uint16_t* p) {
+  return __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(p));
+}
+template <> __device__ __forceinline__ long load_frag<P_FP8>(const uint8_t* p) {
+  return __builtin_bit_cast(long, *reinterpret_cast<const uint2*>(p));
+}
+
+// ------------------------------------------------------------------ input element access
+template <int IN> struct InT;
+template <> struct InT<IN_U16> { using T = uint16_t; };
+template <> struct InT<IN_F32> { using T = float; };
+template <> struct InT<IN_F64> { using T = double; };
+
+template <typename T> __device__ __forceinline__ double to_d(T v) { return (double)v; }
+
+// Eight consecutive input values from a 16-byte aligned address (vector loads).
+__device__ __forceinline__ void load8(const uint16_t* p, uint16_t v[8]) {
+  const uint4 q = *reinterpret_cast<const uint4*>(p);
+  v[0] = q.x & 0xffff; v[1] = q.x >> 16; v[2] = q.y & 0xffff; v[3] = q.y >> 16;
+  v[4] = q.z & 0xffff; v[5] = q.z >> 16; v[6] = q.w & 0xffff; v[7] = q.w >> 16;
+}
+__device__ __forceinline__ void load8(const float* p, float v[8]) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void load8(const double* p, double v[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 a = *reinterpret_cast<const double2*>(p + 2 * i);
+    v[2 * i] = a.x; v[2 * i + 1] = a.y;
+  }
+}
+
+// ------------------------------------------------------------------ wave reductions
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ batch descriptors
+// One batch = a run of consecutive blocks of one stream pushed together
+// (same B, S, input type and precisions).  Scratch arrays are strided per
+// block.  The descriptors travel by value in the kernel arguments.
+struct BatchDesc {
+  const void* x;          // BIL input of the whole batch [lines][B][S]
+  int B, Bp, S;           // bands, padded bands (multiple of 16), samples
+  int nblk;               // blocks in the batch
+  int blk_lines;          // lines of every block but the last
+  int last_lines;         // lines of the last block
+  int cpl;                // chunks (of KC samples) per line
+  int ks, ks_last;        // covariance split count per block / for the last block
+  int nsr, nsup;          // super-rows ceil(Bp/64); lower super-tiles nsr(nsr+1)/2
+  int vec_ok;             // 16-byte vector loads of input rows are aligned
+  int ddof;
+  double rho;             // ridge: lambda = rho * tr(Sigma) / B
+  uint64_t reset_bits;    // bit b: block b starts a new statistics window
+  int64_t n_in;           // window pixel count before the batch
+  // statistics scratch
+  double* shift;          // [nblk][Bp] per-block centring shift (FP32-representable on mixed paths)
+  void* part;             // [nblk][ks][nsup][64*64] centred scatter partials (float, or double on FP64)
+  double* psum;           // [nblk][ks][Bp] raw per-band sums of each split (written by diagonal super-tiles)
+  double* mu_snap;        // [nblk][Bp] window mean after block b
+  double* m2_snap;        // [nblk][Bp*Bp] window scatter matrix after block b (lower triangle)
+  double* n_snap;         // [nblk] window pixel count after block b
+  // resident window state (ping-pong between batches)
+  const double* s1_in; double* s1_out;   // [Bp] raw band sums of the window
+  const double* m2_in; double* m2_out;   // [Bp*Bp] scatter matrix of the window (lower)
+  // factorisation
+  double* w64;            // [nblk][Bp*Bp] W = L^{-1} S (row-major lower, FP64)
+  double* wt64;           // [nblk][Bp*Bp] scratch: transpose of the partial inverse
+  void* wlp;              // [nblk][Bp*Bp] whitening operand in whiten precision, scaled
+  float* iscale;          // [nblk][Bp] input scale 2^-e_k applied to centred values
+  float* oscale;          // [nblk][Bp] output row scale 2^f_i
+  int* status;            // [nblk] 0 ok, 1 singular, 2 not ready
+  unsigned int* nsing;    // stream counter of singular blocks
+  void* scores;           // scores of the batch's pixels (float, or double on FP64 whitening)
+};
+
+struct LaunchSet {
+  int nb;                 // batches in this launch
+  int wg0[MAXB + 1];      // prefix of workgroup counts per batch
+  BatchDesc d[MAXB];
+};
+
+__device__ __forceinline__ int find_batch(const LaunchSet& ls, int wg, int& local) {
+  int b = 0;
+  while (b + 1 < ls.nb && wg >= ls.wg0[b + 1]) ++b;
+  local = wg - ls.wg0[b];
+  return b;
+}
+
+__device__ __forceinline__ int blk_lines_of(const BatchDesc& d, int b) {
+  return b == d.nblk - 1 ? d.last_lines : d.blk_lines;
+}
+__device__ __forceinline__ int ks_of(const BatchDesc& d, int b) {
+  return b == d.nblk - 1 ? d.ks_last : d.ks;
+}
+// Super-tile index -> (I, J), I >= J, row-major over the lower triangle.
+__device__ __forceinline__ void sup_ij(int sup, int& I, int& J) {
+  I = 0;
+  while ((I + 1) * (I + 2) / 2 <= sup) ++I;
+  J = sup - I * (I + 1) / 2;
+}
+
+}  // namespace rxk

@@ -1,0 +1,1018 @@
+// Host runtime behind include/rx.h: stream contexts, block splitting,
+// batch descriptors, kernel sequencing, the pending-score FIFO, masks,
+// checkpoint hooks and the multi-stream server.
+//
+// Per batch of blocks (one stream) the device work is five launches on one
+// HIP stream:  shift -> covariance product -> merge -> FP64 factor ->
+// whitening + score.  A server step packs one batch from each of many
+// streams into the same five launches (up to MAXB batches per launch,
+// grouped by input type and precision).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rx.h"
+#include "rx_dev.h"
+
+using namespace rxk;
+
+extern "C" hipError_t rxk_launch_stats(int in_type, int prec, const LaunchSet* ls_shift, const LaunchSet* ls_syrk,
+                                       const LaunchSet* ls_merge, int wg_shift, int wg_syrk, int wg_merge,
+                                       hipStream_t st);
+extern "C" hipError_t rxk_launch_factor(int wprec, const LaunchSet* ls, int wg, int Bw, hipStream_t st);
+extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const LaunchSet* ls, int wg, int Bw,
+                                        hipStream_t st);
+extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mode, double tau, int64_t k,
+                                      uint32_t* bits, void* scratch, hipStream_t st);
+
+static_assert(sizeof(LaunchSet) < 4000, "kernel-argument descriptor set too large");
+
+// ---------------------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static rx_status fail(rx_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPC(call)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(RX_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------- device buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+static rx_status dev_ensure(DevBuf& b, size_t bytes, hipStream_t st) {
+  if (bytes <= b.cap) return RX_OK;
+  if (b.p) {
+    HIPC(hipStreamSynchronize(st));
+    HIPC(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  const size_t nb = std::max<size_t>(bytes, 256);
+  if (hipMalloc(&b.p, nb) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RX_E_NOMEM, "hipMalloc(%zu bytes) failed", nb);
+  }
+  b.cap = nb;
+  return RX_OK;
+}
+
+static void dev_free(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// ---------------------------------------------------------------------------- geometry
+static constexpr uint32_t kMagic = 0x52585354u;   // "RXST"
+static constexpr int kSplitChunks = 64;            // pixel chunks per covariance split (4096 px)
+static constexpr int kMaxBlocksPerBatch = 64;      // reset bits are a 64-bit mask
+
+static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+static int pad16(int b) { return 16 * ceil_div(b, 16); }
+static int pad32(int b) { return 32 * ceil_div(b, 32); }
+static size_t in_elem_size(int t) { return t == RX_IN_U16 ? 2 : (t == RX_IN_F32 ? 4 : 8); }
+static int splits_for(int lines, int cpl) { return std::min(64, std::max(1, ceil_div((int64_t)lines * cpl, kSplitChunks))); }
+
+struct Block {
+  int64_t line0;   // first line within the push
+  int lines;
+  bool reset;
+};
+
+struct Sizes {
+  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status;
+};
+
+static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
+  const int Bp = pad16(B), Bw = pad32(Bp);
+  const int nsr = ceil_div(Bp, SUP), nsup = nsr * (nsr + 1) / 2;
+  const int ks = splits_for(blk_lines, ceil_div(S, KC));
+  const size_t psz = sp == RX_FP64 ? 8 : 4;
+  Sizes z;
+  z.shift = (size_t)nblk * Bp * 8;
+  z.part = (size_t)nblk * ks * nsup * SUP * SUP * psz;
+  z.psum = (size_t)nblk * ks * Bp * 8;
+  z.mu = (size_t)nblk * Bp * 8;
+  z.m2 = (size_t)nblk * Bp * Bp * 8;
+  z.nsnap = (size_t)nblk * 8;
+  z.w64 = (size_t)nblk * Bp * Bp * 8;
+  z.wlp = (size_t)nblk * Bp * Bw * 4;
+  z.scl = (size_t)nblk * Bp * 4;
+  z.status = (size_t)nblk * 4;
+  return z;
+}
+
+// ---------------------------------------------------------------------------- stream
+struct rx_stream {
+  uint32_t magic = kMagic;
+  rx_config cfg{};
+  int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
+  size_t esz = 0;
+  int dev = 0;
+  hipStream_t st = nullptr;
+  bool own_st = false;
+  hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr;
+  rx_server* srv = nullptr;
+  size_t footprint = 0;
+  // resident window state (ping-pong)
+  DevBuf s1[2], m2[2];
+  int cur = 0;
+  int64_t N = 0;
+  int64_t lines_seen = 0;
+  // batch scratch
+  DevBuf shift, part, psum, mu, m2s, nsnap, w64, wt64, wlp, isc, osc, status, nsing;
+  unsigned last_nsing = 0;
+  // pending scores
+  DevBuf pend[2];
+  int pcur = 0;
+  int64_t head = 0, tail = 0;
+  int sc_f64 = 0;
+  // host input staging
+  DevBuf stage;
+  void* host_pin = nullptr;
+  size_t host_pin_cap = 0;
+  bool stage_busy = false;
+  // masks and conversions
+  DevBuf maskbits, maskscr, cvt;
+  // last factor
+  int64_t last_w_off = -1;
+  // optional per-phase timing with HIP events on the stream the kernels run on
+  bool prof = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_open;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  rx_counters cnt{};
+  rx_status sticky = RX_OK;
+};
+
+static rx_status check_stream(rx_stream* s) {
+  if (!s) return fail(RX_E_ARG, "null stream");
+  if (s->magic != kMagic) return fail(RX_E_STATE, "stream handle is not live");
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- server (declared early)
+struct Pending {
+  rx_stream* s;
+  const void* x;
+  int64_t lines;
+  uint64_t tag;
+};
+struct InFlight {
+  hipEvent_t ev;
+  std::vector<std::pair<rx_stream*, uint64_t>> items;
+};
+struct rx_server {
+  uint32_t magic = 0x52585356u;   // "RXSV"
+  size_t budget = 0, used = 0;
+  int max_streams = 0, n_streams = 0;
+  int dev = 0;
+  hipStream_t st = nullptr;
+  std::deque<Pending> queue;
+  std::deque<InFlight> inflight;
+  std::vector<hipEvent_t> free_events;
+  std::mutex mu;
+};
+
+// ---------------------------------------------------------------------------- config
+extern "C" rx_status rx_config_init(rx_config* cfg, int32_t bands, int32_t samples) {
+  if (!cfg) return fail(RX_E_ARG, "null config");
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->struct_size = sizeof(rx_config);
+  cfg->bands = bands;
+  cfg->samples = samples;
+  cfg->in_type = RX_IN_U16;
+  cfg->bit_depth = 12;
+  cfg->layout = RX_BIL;
+  cfg->syrk_prec = RX_BF16;
+  cfg->whiten_prec = RX_BF16;
+  return RX_OK;
+}
+
+static rx_status validate(const rx_config* c) {
+  if (!c) return fail(RX_E_ARG, "null config");
+  if (c->struct_size != sizeof(rx_config)) return fail(RX_E_ARG, "struct_size %u != %zu", c->struct_size, sizeof(rx_config));
+  if (c->bands < 1 || c->bands > RX_MAX_BANDS) return fail(RX_E_ARG, "bands must be in [1, %d]", RX_MAX_BANDS);
+  if (c->samples < 1) return fail(RX_E_ARG, "samples must be >= 1");
+  if (c->in_type < RX_IN_U16 || c->in_type > RX_IN_F64) return fail(RX_E_ARG, "bad in_type");
+  if (c->layout != RX_BIL) return fail(RX_E_ARG, "only the BIL layout is supported");
+  if (c->syrk_prec < RX_FP64 || c->syrk_prec > RX_FP16) return fail(RX_E_ARG, "syrk_prec must be FP64, FP32, BF16 or FP16");
+  if (c->whiten_prec < RX_FP64 || c->whiten_prec > RX_FP8_E4M3) return fail(RX_E_ARG, "bad whiten_prec");
+  if (c->ddof != 0 && c->ddof != 1) return fail(RX_E_ARG, "ddof must be 0 or 1");
+  if (c->block_lines < 0 || c->window_lines < 0) return fail(RX_E_ARG, "block_lines and window_lines must be >= 0");
+  if (!(c->ridge_rel >= 0.0) || !std::isfinite(c->ridge_rel)) return fail(RX_E_ARG, "ridge_rel must be finite and >= 0");
+  if (c->flags != 0) return fail(RX_E_ARG, "flags must be 0");
+  if (c->in_type == RX_IN_U16 && (c->bit_depth < 0 || c->bit_depth > 16)) return fail(RX_E_ARG, "bit_depth must be in [0, 16]");
+  return RX_OK;
+}
+
+static size_t stream_bytes(const rx_config* c, int max_block_lines) {
+  const int Bp = pad16(c->bands);
+  const Sizes z = scratch_sizes(c->bands, c->samples, c->syrk_prec, 1, std::max(1, max_block_lines));
+  const size_t state = 2 * ((size_t)Bp * 8 + (size_t)Bp * Bp * 8);
+  const size_t scr = z.shift + z.part + z.psum + z.mu + z.m2 + z.nsnap + 2 * z.w64 + z.wlp + 2 * z.scl + z.status;
+  const size_t esz = c->whiten_prec == RX_FP64 ? 8 : 4;
+  const size_t pend = 2 * (size_t)std::max(1, max_block_lines) * c->samples * esz;
+  return state + scr + pend;
+}
+
+extern "C" rx_status rx_stream_footprint(const rx_config* cfg, int32_t max_block_lines, size_t* bytes) {
+  rx_status r = validate(cfg);
+  if (r != RX_OK) return r;
+  if (!bytes || max_block_lines < 1) return fail(RX_E_ARG, "null bytes or max_block_lines < 1");
+  *bytes = stream_bytes(cfg, max_block_lines);
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- init / destroy
+static void free_stream(rx_stream* s) {
+  DevBuf* bufs[] = {&s->s1[0], &s->s1[1], &s->m2[0], &s->m2[1], &s->shift, &s->part, &s->psum, &s->mu,
+                    &s->m2s, &s->nsnap, &s->w64, &s->wt64, &s->wlp, &s->isc, &s->osc, &s->status,
+                    &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
+  for (DevBuf* b : bufs) dev_free(*b);
+  if (s->host_pin) (void)hipHostFree(s->host_pin);
+  s->host_pin = nullptr;
+  for (auto& pe : s->prof_open) { s->prof_pool.push_back(pe.second.first); s->prof_pool.push_back(pe.second.second); }
+  for (hipEvent_t e : s->prof_pool) (void)hipEventDestroy(e);
+  s->prof_pool.clear();
+  s->prof_open.clear();
+  if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+  if (s->ev_done) (void)hipEventDestroy(s->ev_done);
+  if (s->ev_stage) (void)hipEventDestroy(s->ev_stage);
+  if (s->own_st && s->st) (void)hipStreamDestroy(s->st);
+  s->magic = 0;
+}
+
+static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
+  const Sizes z = scratch_sizes(s->B, s->S, s->sp, nblk, blk_lines);
+  rx_status r;
+  if ((r = dev_ensure(s->shift, z.shift, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->part, z.part, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->psum, z.psum, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->mu, z.mu, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->m2s, z.m2, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->nsnap, z.nsnap, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->w64, z.w64, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->wt64, z.w64, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->wlp, z.wlp, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->isc, z.scl, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->osc, z.scl, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->status, z.status, s->st)) != RX_OK) return r;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** out) {
+  if (!out) return fail(RX_E_ARG, "null output handle");
+  *out = nullptr;
+  rx_status r = validate(cfg);
+  if (r != RX_OK) return r;
+  int ndev = 0;
+  HIPC(hipGetDeviceCount(&ndev));
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(RX_E_ARG, "device %d not present (%d devices)", cfg->device, ndev);
+  if (srv && srv->dev != cfg->device) return fail(RX_E_ARG, "stream device differs from the server's");
+  HIPC(hipSetDevice(cfg->device));
+
+  rx_stream* s = new rx_stream();
+  s->cfg = *cfg;
+  s->B = cfg->bands;
+  s->Bp = pad16(s->B);
+  s->Bw = pad32(s->Bp);
+  s->S = cfg->samples;
+  s->in_type = cfg->in_type;
+  s->sp = cfg->syrk_prec;
+  s->wp = cfg->whiten_prec;
+  s->cpl = ceil_div(s->S, KC);
+  s->esz = in_elem_size(s->in_type);
+  s->dev = cfg->device;
+  s->sc_f64 = s->wp == RX_FP64 ? 1 : 0;
+
+  auto bail = [&](rx_status st) {
+    std::string keep = g_err;
+    free_stream(s);
+    delete s;
+    g_err = keep;
+    return st;
+  };
+  if (srv) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    const int mbl = cfg->block_lines > 0 ? cfg->block_lines : 128;
+    const size_t need = stream_bytes(cfg, mbl);
+    if (srv->n_streams >= srv->max_streams) { delete s; return fail(RX_E_BUDGET, "server has no free stream slot"); }
+    if (srv->used + need > srv->budget) {
+      delete s;
+      return fail(RX_E_BUDGET, "stream needs %zu bytes, %zu of %zu left", need, srv->budget - srv->used, srv->budget);
+    }
+    srv->used += need;
+    srv->n_streams += 1;
+    s->srv = srv;
+    s->footprint = need;
+    s->st = srv->st;
+  } else {
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipStreamCreate failed"));
+    s->own_st = true;
+  }
+  if (hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_done, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_stage, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
+  const size_t s1b = (size_t)s->Bp * 8, m2b = (size_t)s->Bp * s->Bp * 8;
+  for (int i = 0; i < 2; ++i) {
+    if ((r = dev_ensure(s->s1[i], s1b, s->st)) != RX_OK) return bail(r);
+    if ((r = dev_ensure(s->m2[i], m2b, s->st)) != RX_OK) return bail(r);
+    if (hipMemsetAsync(s->s1[i].p, 0, s1b, s->st) != hipSuccess || hipMemsetAsync(s->m2[i].p, 0, m2b, s->st) != hipSuccess)
+      return bail(fail(RX_E_DEVICE, "hipMemsetAsync failed"));
+  }
+  if ((r = dev_ensure(s->nsing, 256, s->st)) != RX_OK) return bail(r);
+  if (hipMemsetAsync(s->nsing.p, 0, 256, s->st) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipMemsetAsync failed"));
+  if (s->srv) {
+    const int mbl = cfg->block_lines > 0 ? cfg->block_lines : 128;
+    if ((r = alloc_scratch(s, 1, mbl)) != RX_OK) return bail(r);
+    if ((r = dev_ensure(s->pend[0], (size_t)2 * mbl * s->S * (s->sc_f64 ? 8 : 4), s->st)) != RX_OK) return bail(r);
+  }
+  if (hipStreamSynchronize(s->st) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipStreamSynchronize failed"));
+  *out = s;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_destroy(rx_stream* s) {
+  if (!s) return RX_OK;
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  (void)hipSetDevice(s->dev);
+  (void)hipStreamSynchronize(s->st);
+  if (s->srv) {
+    rx_server* srv = s->srv;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (auto it = srv->queue.begin(); it != srv->queue.end();) it = (it->s == s) ? srv->queue.erase(it) : it + 1;
+    for (auto& f : srv->inflight)
+      for (auto& it : f.items)
+        if (it.first == s) it.first = nullptr;
+    srv->used -= s->footprint;
+    srv->n_streams -= 1;
+  }
+  free_stream(s);
+  delete s;
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- pending FIFO
+static rx_status pending_reserve(rx_stream* s, int64_t npx) {
+  const size_t es = s->sc_f64 ? 8 : 4;
+  const int64_t live = s->tail - s->head;
+  DevBuf& cur = s->pend[s->pcur];
+  if ((size_t)(s->tail + npx) * es <= cur.cap) return RX_OK;
+  DevBuf& alt = s->pend[1 - s->pcur];
+  const size_t need = (size_t)(live + npx) * es;
+  rx_status r = dev_ensure(alt, std::max(need, cur.cap * 2), s->st);
+  if (r != RX_OK) return r;
+  if (live > 0)
+    HIPC(hipMemcpyAsync(alt.p, static_cast<char*>(cur.p) + (size_t)s->head * es, (size_t)live * es,
+                        hipMemcpyDeviceToDevice, s->st));
+  s->pcur = 1 - s->pcur;
+  s->head = 0;
+  s->tail = live;
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- batch preparation
+struct Job {
+  rx_stream* s;
+  BatchDesc d;
+  int in_type, sp, wp, Bw;
+  int wg_shift, wg_syrk, wg_merge, wg_factor, wg_whiten;
+};
+
+// Cut n_lines starting at stream line `pos` into blocks.
+static void cut_blocks(const rx_stream* s, int64_t pos, int64_t n_lines, std::vector<Block>& out) {
+  int64_t off = 0;
+  while (off < n_lines) {
+    int64_t take = n_lines - off;
+    if (s->cfg.block_lines > 0) take = std::min<int64_t>(take, s->cfg.block_lines);
+    const int64_t R = s->cfg.window_lines;
+    bool reset = false;
+    if (R > 0) {
+      take = std::min<int64_t>(take, R - (pos + off) % R);
+      reset = ((pos + off) % R) == 0;
+    }
+    out.push_back(Block{off, (int)take, reset});
+    off += take;
+  }
+}
+
+// Fill a job for blocks[i0, i1) of a push whose lines start at x.  Updates
+// the host copy of N and the pending tail; reserves scratch.
+static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Block>& blks, size_t i0, size_t i1,
+                             Job& j, bool& notready) {
+  const int nblk = (int)(i1 - i0);
+  const int L = blks[i0].lines, last = blks[i1 - 1].lines;
+  rx_status r = alloc_scratch(s, nblk, L);
+  if (r != RX_OK) return r;
+  int64_t lines = 0;
+  for (size_t i = i0; i < i1; ++i) lines += blks[i].lines;
+  const int64_t npx = lines * s->S;
+  if ((r = pending_reserve(s, npx)) != RX_OK) return r;
+
+  BatchDesc& d = j.d;
+  std::memset(&d, 0, sizeof d);
+  d.x = static_cast<const char*>(x) + (size_t)blks[i0].line0 * s->B * s->S * s->esz;
+  d.B = s->B;
+  d.Bp = s->Bp;
+  d.S = s->S;
+  d.nblk = nblk;
+  d.blk_lines = L;
+  d.last_lines = last;
+  d.cpl = s->cpl;
+  d.ks = splits_for(L, s->cpl);
+  d.ks_last = splits_for(last, s->cpl);
+  d.nsr = ceil_div(s->Bp, SUP);
+  d.nsup = d.nsr * (d.nsr + 1) / 2;
+  d.vec_ok = ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0) && (((size_t)s->S * s->esz) % 16 == 0);
+  d.ddof = s->cfg.ddof;
+  d.rho = s->cfg.ridge_rel;
+  d.n_in = s->N;
+  uint64_t rb = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const Block& bk = blks[i0 + b];
+    if (bk.reset) {
+      rb |= 1ull << b;
+      s->N = 0;
+    }
+    s->N += (int64_t)bk.lines * s->S;
+    if (s->cfg.ridge_rel == 0.0 && s->N <= s->B) {
+      notready = true;
+      s->cnt.notready_blocks += 1;
+    }
+  }
+  d.reset_bits = rb;
+  d.shift = static_cast<double*>(s->shift.p);
+  d.part = s->part.p;
+  d.psum = static_cast<double*>(s->psum.p);
+  d.mu_snap = static_cast<double*>(s->mu.p);
+  d.m2_snap = static_cast<double*>(s->m2s.p);
+  d.n_snap = static_cast<double*>(s->nsnap.p);
+  d.s1_in = static_cast<const double*>(s->s1[s->cur].p);
+  d.s1_out = static_cast<double*>(s->s1[1 - s->cur].p);
+  d.m2_in = static_cast<const double*>(s->m2[s->cur].p);
+  d.m2_out = static_cast<double*>(s->m2[1 - s->cur].p);
+  d.w64 = static_cast<double*>(s->w64.p);
+  d.wt64 = static_cast<double*>(s->wt64.p);
+  d.wlp = s->wlp.p;
+  d.iscale = static_cast<float*>(s->isc.p);
+  d.oscale = static_cast<float*>(s->osc.p);
+  d.status = static_cast<int*>(s->status.p);
+  d.nsing = static_cast<unsigned int*>(s->nsing.p);
+  d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
+
+  j.s = s;
+  j.in_type = s->in_type;
+  j.sp = s->sp;
+  j.wp = s->wp;
+  j.Bw = s->Bw;
+  j.wg_shift = nblk * (s->Bp / 4);
+  j.wg_syrk = d.nsup * ((nblk - 1) * d.ks + d.ks_last);
+  j.wg_merge = d.nsup;
+  j.wg_factor = nblk;
+  j.wg_whiten = (int)(lines * s->cpl);
+
+  s->cur ^= 1;
+  s->tail += npx;
+  s->last_w_off = (int64_t)(nblk - 1) * s->Bp * s->Bp;
+  s->cnt.blocks += nblk;
+  return RX_OK;
+}
+
+// Phase timing: a pair of events around one phase's launches.
+static rx_status prof_mark(rx_stream* s, int phase, bool begin, hipStream_t st) {
+  if (!s || !s->prof) return RX_OK;
+  auto take = [&]() -> hipEvent_t {
+    if (!s->prof_pool.empty()) { hipEvent_t e = s->prof_pool.back(); s->prof_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  };
+  if (begin) {
+    hipEvent_t a = take();
+    HIPC(hipEventRecord(a, st));
+    s->prof_open.push_back({phase, {a, nullptr}});
+  } else {
+    hipEvent_t b = take();
+    HIPC(hipEventRecord(b, st));
+    s->prof_open.back().second.second = b;
+  }
+  return RX_OK;
+}
+
+static rx_status prof_collect(rx_stream* s) {
+  for (auto& pe : s->prof_open) {
+    float ms = 0.0f;
+    if (pe.second.second) {
+      HIPC(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+      s->prof_ms[pe.first] += ms;
+      s->prof_n[pe.first] += 1;
+      s->prof_pool.push_back(pe.second.second);
+    }
+    s->prof_pool.push_back(pe.second.first);
+  }
+  s->prof_open.clear();
+  return RX_OK;
+}
+
+// Launch the five phases for a set of jobs (each stream at most once).
+// prof (nullable): stream whose phase timers bracket the launches.
+static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* prof = nullptr) {
+  auto run_groups = [&](auto key, auto launch) -> rx_status {
+    std::vector<bool> done(jobs.size(), false);
+    for (size_t a = 0; a < jobs.size(); ++a) {
+      if (done[a]) continue;
+      std::vector<size_t> grp;
+      for (size_t c = a; c < jobs.size(); ++c)
+        if (!done[c] && key(jobs[c]) == key(jobs[a])) grp.push_back(c);
+      for (size_t g0 = 0; g0 < grp.size(); g0 += MAXB) {
+        const size_t g1 = std::min(grp.size(), g0 + MAXB);
+        rx_status r = launch(grp, g0, g1);
+        if (r != RX_OK) return r;
+      }
+      for (size_t c : grp) done[c] = true;
+    }
+    return RX_OK;
+  };
+  auto fill = [&](LaunchSet& ls, const std::vector<size_t>& grp, size_t g0, size_t g1, int Job::*wg) {
+    ls.nb = (int)(g1 - g0);
+    ls.wg0[0] = 0;
+    for (size_t i = g0; i < g1; ++i) {
+      ls.d[i - g0] = jobs[grp[i]].d;
+      ls.wg0[i - g0 + 1] = ls.wg0[i - g0] + jobs[grp[i]].*wg;
+    }
+    return ls.wg0[ls.nb];
+  };
+  rx_status r = run_groups([](const Job& j) { return j.in_type * 16 + j.sp; },
+                           [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
+                             LaunchSet a, b, c;
+                             const int n1 = fill(a, grp, g0, g1, &Job::wg_shift);
+                             const int n2 = fill(b, grp, g0, g1, &Job::wg_syrk);
+                             const int n3 = fill(c, grp, g0, g1, &Job::wg_merge);
+                             const int it = jobs[grp[g0]].in_type, sp = jobs[grp[g0]].sp;
+                             rx_status q;
+                             if ((q = prof_mark(prof, 0, true, st)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, &a, &b, &c, n1, 0, 0, st));
+                             if ((q = prof_mark(prof, 0, false, st)) != RX_OK) return q;
+                             if ((q = prof_mark(prof, 1, true, st)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, &a, &b, &c, 0, n2, 0, st));
+                             if ((q = prof_mark(prof, 1, false, st)) != RX_OK) return q;
+                             if ((q = prof_mark(prof, 2, true, st)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, &a, &b, &c, 0, 0, n3, st));
+                             return prof_mark(prof, 2, false, st);
+                           });
+  if (r != RX_OK) return r;
+  r = run_groups([](const Job& j) { return j.wp * 1024 + j.Bw; },
+                 [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
+                   LaunchSet a;
+                   const int n = fill(a, grp, g0, g1, &Job::wg_factor);
+                   rx_status q;
+                   if ((q = prof_mark(prof, 3, true, st)) != RX_OK) return q;
+                   HIPC(rxk_launch_factor(jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw, st));
+                   return prof_mark(prof, 3, false, st);
+                 });
+  if (r != RX_OK) return r;
+  return run_groups([](const Job& j) { return (j.in_type * 16 + j.wp) * 1024 + j.Bw; },
+                    [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
+                      LaunchSet a;
+                      const int n = fill(a, grp, g0, g1, &Job::wg_whiten);
+                      rx_status q;
+                      if ((q = prof_mark(prof, 4, true, st)) != RX_OK) return q;
+                      HIPC(rxk_launch_whiten(jobs[grp[g0]].in_type, jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw, st));
+                      return prof_mark(prof, 4, false, st);
+                    });
+}
+
+// ---------------------------------------------------------------------------- push
+static rx_status stage_host_input(rx_stream* s, const void* lines, size_t bytes, const void** x) {
+  if (s->stage_busy) {
+    HIPC(hipEventSynchronize(s->ev_stage));
+    s->stage_busy = false;
+  }
+  if (bytes > s->host_pin_cap) {
+    if (s->host_pin) HIPC(hipHostFree(s->host_pin));
+    s->host_pin = nullptr;
+    s->host_pin_cap = 0;
+    if (hipHostMalloc(&s->host_pin, bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RX_E_NOMEM, "hipHostMalloc(%zu) failed", bytes);
+    }
+    s->host_pin_cap = bytes;
+  }
+  rx_status r = dev_ensure(s->stage, bytes, s->st);
+  if (r != RX_OK) return r;
+  std::memcpy(s->host_pin, lines, bytes);
+  HIPC(hipMemcpyAsync(s->stage.p, s->host_pin, bytes, hipMemcpyHostToDevice, s->st));
+  HIPC(hipEventRecord(s->ev_stage, s->st));
+  s->stage_busy = true;
+  *x = s->stage.p;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_lines, int32_t is_device_ptr,
+                                   void* hip_stream) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (s->srv) return fail(RX_E_STATE, "served streams take blocks through rx_server_submit");
+  if (!lines) return fail(RX_E_ARG, "null lines");
+  if (n_lines < 1) return fail(RX_E_ARG, "n_lines must be >= 1");
+  HIPC(hipSetDevice(s->dev));
+  const size_t bytes = (size_t)n_lines * s->B * s->S * s->esz;
+  const void* x = lines;
+  if (!is_device_ptr) {
+    if ((r = stage_host_input(s, lines, bytes, &x)) != RX_OK) return r;
+  } else {
+    HIPC(hipEventRecord(s->ev_in, static_cast<hipStream_t>(hip_stream)));
+    HIPC(hipStreamWaitEvent(s->st, s->ev_in, 0));
+  }
+  std::vector<Block> blks;
+  cut_blocks(s, s->lines_seen, n_lines, blks);
+  bool notready = false;
+  size_t i = 0;
+  while (i < blks.size()) {
+    size_t k = i + 1;
+    while (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines == blks[i].lines) ++k;
+    if (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines < blks[i].lines) ++k;
+    std::vector<Job> jobs(1);
+    if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready)) != RX_OK) return r;
+    if ((r = launch_jobs(jobs, s->st, s)) != RX_OK) return r;
+    i = k;
+  }
+  s->lines_seen += n_lines;
+  s->cnt.lines_pushed += n_lines;
+  if (notready) return fail(RX_E_NOTREADY, "a block was scored with N <= B and no ridge; its scores are NaN");
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- outputs
+__global__ void k_f64_to_f32(const double* a, float* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_f32_to_f64(const float* a, double* b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+static rx_status pop_scores(rx_stream* s, void* out, int want_f64, int64_t max_px, int64_t* n_written,
+                            int32_t out_is_device, void* hip_stream) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!n_written || (!out && max_px > 0) || max_px < 0) return fail(RX_E_ARG, "bad output arguments");
+  HIPC(hipSetDevice(s->dev));
+  const int64_t n = std::min(max_px, s->tail - s->head);
+  *n_written = n;
+  if (n == 0) return RX_OK;
+  const size_t es = s->sc_f64 ? 8 : 4, eo = want_f64 ? 8 : 4;
+  const char* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * es;
+  const void* from = src;
+  if ((int)s->sc_f64 != want_f64) {
+    if ((r = dev_ensure(s->cvt, (size_t)n * eo, s->st)) != RX_OK) return r;
+    const int g = ceil_div(n, 256);
+    if (want_f64) hipLaunchKernelGGL(k_f32_to_f64, dim3(g), dim3(256), 0, s->st, (const float*)src, (double*)s->cvt.p, n);
+    else hipLaunchKernelGGL(k_f64_to_f32, dim3(g), dim3(256), 0, s->st, (const double*)src, (float*)s->cvt.p, n);
+    HIPC(hipGetLastError());
+    from = s->cvt.p;
+  }
+  if (out_is_device) {
+    HIPC(hipMemcpyAsync(out, from, (size_t)n * eo, hipMemcpyDeviceToDevice, s->st));
+    HIPC(hipEventRecord(s->ev_done, s->st));
+    HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
+  } else {
+    HIPC(hipStreamSynchronize(s->st));
+    HIPC(hipMemcpy(out, from, (size_t)n * eo, hipMemcpyDeviceToHost));
+  }
+  s->head += n;
+  if (s->head == s->tail) s->head = s->tail = 0;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_scores(rx_stream* s, float* out, int64_t max_px, int64_t* n_written, int32_t out_is_device,
+                               void* hip_stream) {
+  return pop_scores(s, out, 0, max_px, n_written, out_is_device, hip_stream);
+}
+extern "C" rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_written,
+                                   int32_t out_is_device, void* hip_stream) {
+  return pop_scores(s, out, 1, max_px, n_written, out_is_device, hip_stream);
+}
+
+extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits, int64_t max_bytes,
+                             int64_t* n_px, int32_t out_is_device, void* hip_stream) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!n_px) return fail(RX_E_ARG, "null n_px");
+  if (mode < RX_THR_ABS || mode > RX_THR_TOPK) return fail(RX_E_ARG, "bad threshold mode");
+  if (mode == RX_THR_TOPK && k < 0) return fail(RX_E_ARG, "k must be >= 0");
+  if (mode != RX_THR_TOPK && std::isnan(tau)) return fail(RX_E_ARG, "tau is NaN");
+  HIPC(hipSetDevice(s->dev));
+  const int64_t n = s->tail - s->head;
+  const int64_t nbytes = (n + 7) / 8;
+  *n_px = n;
+  if (n == 0) return RX_OK;
+  if (!bits || max_bytes < nbytes) return fail(RX_E_ARG, "mask buffer needs %lld bytes", (long long)nbytes);
+  const int64_t words = (n + 31) / 32;
+  if ((r = dev_ensure(s->maskbits, (size_t)words * 4, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->maskscr, 4096, s->st)) != RX_OK) return r;
+  const void* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * (s->sc_f64 ? 8 : 4);
+  if (mode == RX_THR_TOPK && k == 0) {
+    HIPC(hipMemsetAsync(s->maskbits.p, 0, (size_t)words * 4, s->st));
+  } else {
+    HIPC(rxk_launch_mask(src, s->sc_f64, n, mode, tau, k, static_cast<uint32_t*>(s->maskbits.p), s->maskscr.p, s->st));
+  }
+  if (out_is_device) {
+    HIPC(hipMemcpyAsync(bits, s->maskbits.p, (size_t)nbytes, hipMemcpyDeviceToDevice, s->st));
+    HIPC(hipEventRecord(s->ev_done, s->st));
+    HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
+  } else {
+    HIPC(hipStreamSynchronize(s->st));
+    HIPC(hipMemcpy(bits, s->maskbits.p, (size_t)nbytes, hipMemcpyDeviceToHost));
+  }
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- sync / counters / hooks
+static rx_status refresh_counters(rx_stream* s) {
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipStreamSynchronize(s->st));
+  unsigned ns = 0;
+  HIPC(hipMemcpy(&ns, s->nsing.p, sizeof ns, hipMemcpyDeviceToHost));
+  if (ns > s->last_nsing && s->sticky == RX_OK) s->sticky = RX_E_SINGULAR;
+  s->last_nsing = ns;
+  s->cnt.singular_blocks = ns;
+  s->cnt.pending_px = s->tail - s->head;
+  s->cnt.window_px = s->N;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_wait(rx_stream* s, void* hip_stream) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipEventRecord(s->ev_done, s->st));
+  HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
+  return RX_OK;
+}
+
+extern "C" rx_status rx_sync(rx_stream* s) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if ((r = refresh_counters(s)) != RX_OK) return r;
+  const rx_status st = s->sticky;
+  s->sticky = RX_OK;
+  if (st == RX_E_SINGULAR) return fail(st, "a block hit a non-positive pivot in the FP64 Cholesky; its scores are NaN");
+  return RX_OK;
+}
+
+extern "C" rx_status rx_get_counters(rx_stream* s, rx_counters* out) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!out) return fail(RX_E_ARG, "null counters");
+  if ((r = refresh_counters(s)) != RX_OK) return r;
+  *out = s->cnt;
+  return RX_OK;
+}
+
+extern "C" const char* rx_last_error(void) { return g_err.c_str(); }
+
+extern "C" rx_status rx_profile(rx_stream* s, int32_t enable) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipStreamSynchronize(s->st));
+  if ((r = prof_collect(s)) != RX_OK) return r;
+  s->prof = enable != 0;
+  for (int i = 0; i < 5; ++i) { s->prof_ms[i] = 0.0; s->prof_n[i] = 0; }
+  return RX_OK;
+}
+
+extern "C" rx_status rx_phase_times(rx_stream* s, double* ms, int64_t* launches) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!ms || !launches) return fail(RX_E_ARG, "null output");
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipStreamSynchronize(s->st));
+  if ((r = prof_collect(s)) != RX_OK) return r;
+  for (int i = 0; i < 5; ++i) { ms[i] = s->prof_ms[i]; launches[i] = s->prof_n[i]; }
+  return RX_OK;
+}
+
+extern "C" rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double* cov) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!n) return fail(RX_E_ARG, "null n");
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipStreamSynchronize(s->st));
+  const int B = s->B, Bp = s->Bp;
+  std::vector<double> s1(Bp), m2((size_t)Bp * Bp);
+  HIPC(hipMemcpy(s1.data(), s->s1[s->cur].p, (size_t)Bp * 8, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(m2.data(), s->m2[s->cur].p, (size_t)Bp * Bp * 8, hipMemcpyDeviceToHost));
+  *n = s->N;
+  if (mean)
+    for (int k = 0; k < B; ++k) mean[k] = s->N > 0 ? s1[k] / (double)s->N : NAN;
+  if (cov) {
+    const double den = (double)(s->N - s->cfg.ddof);
+    for (int i = 0; i < B; ++i)
+      for (int j = 0; j <= i; ++j) cov[(size_t)i * B + j] = cov[(size_t)j * B + i] = m2[(size_t)i * Bp + j] / den;
+  }
+  return RX_OK;
+}
+
+extern "C" rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, const double* cov) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (n < 0 || (n > 0 && (!mean || !cov))) return fail(RX_E_ARG, "bad statistics");
+  if (n > 0 && n <= s->cfg.ddof) return fail(RX_E_ARG, "n must exceed ddof");
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipStreamSynchronize(s->st));
+  const int B = s->B, Bp = s->Bp;
+  std::vector<double> s1(Bp, 0.0), m2((size_t)Bp * Bp, 0.0);
+  if (n > 0) {
+    const double den = (double)(n - s->cfg.ddof);
+    for (int k = 0; k < B; ++k) s1[k] = mean[k] * (double)n;
+    for (int i = 0; i < B; ++i)
+      for (int j = 0; j <= i; ++j) m2[(size_t)i * Bp + j] = cov[(size_t)i * B + j] * den;
+  }
+  HIPC(hipMemcpy(s->s1[s->cur].p, s1.data(), (size_t)Bp * 8, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(s->m2[s->cur].p, m2.data(), (size_t)Bp * Bp * 8, hipMemcpyHostToDevice));
+  s->N = n;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_get_whitener(rx_stream* s, double* w) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!w) return fail(RX_E_ARG, "null output");
+  if (s->last_w_off < 0) return fail(RX_E_STATE, "no block has been factored yet");
+  HIPC(hipSetDevice(s->dev));
+  HIPC(hipStreamSynchronize(s->st));
+  const int B = s->B, Bp = s->Bp;
+  std::vector<double> full((size_t)Bp * Bp);
+  HIPC(hipMemcpy(full.data(), static_cast<double*>(s->w64.p) + s->last_w_off, full.size() * 8, hipMemcpyDeviceToHost));
+  for (int i = 0; i < B; ++i)
+    for (int j = 0; j < B; ++j) w[(size_t)i * B + j] = full[(size_t)i * Bp + j];
+  return RX_OK;
+}
+
+// ---------------------------------------------------------------------------- server
+extern "C" rx_status rx_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32_t device, rx_server** out) {
+  if (!out) return fail(RX_E_ARG, "null output handle");
+  *out = nullptr;
+  if (max_streams < 1) return fail(RX_E_ARG, "max_streams must be >= 1");
+  int ndev = 0;
+  HIPC(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(RX_E_ARG, "device %d not present", device);
+  HIPC(hipSetDevice(device));
+  rx_server* srv = new rx_server();
+  srv->budget = hbm_budget_bytes;
+  srv->max_streams = max_streams;
+  srv->dev = device;
+  if (hipStreamCreateWithFlags(&srv->st, hipStreamNonBlocking) != hipSuccess) {
+    delete srv;
+    return fail(RX_E_DEVICE, "hipStreamCreate failed");
+  }
+  *out = srv;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_destroy(rx_server* srv) {
+  if (!srv) return RX_OK;
+  if (srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  (void)hipSetDevice(srv->dev);
+  if (srv->n_streams > 0) return fail(RX_E_STATE, "destroy the server's %d streams first", srv->n_streams);
+  (void)hipStreamSynchronize(srv->st);
+  for (auto& f : srv->inflight) srv->free_events.push_back(f.ev);
+  for (hipEvent_t e : srv->free_events) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(srv->st);
+  srv->magic = 0;
+  delete srv;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_submit(rx_server* srv, rx_stream* s, const void* lines_dev, int64_t n_lines,
+                                      uint64_t tag) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (s->srv != srv) return fail(RX_E_STATE, "stream is not admitted on this server");
+  if (!lines_dev || n_lines < 1) return fail(RX_E_ARG, "bad block");
+  const int mbl = s->cfg.block_lines > 0 ? s->cfg.block_lines : 128;
+  if (n_lines > mbl) return fail(RX_E_ARG, "block of %lld lines exceeds the stream's %d", (long long)n_lines, mbl);
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->queue.push_back(Pending{s, lines_dev, n_lines, tag});
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  HIPC(hipSetDevice(srv->dev));
+  std::lock_guard<std::mutex> lk(srv->mu);
+  // one block per stream per step (a stream's blocks depend on each other)
+  std::vector<Pending> take;
+  for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+    bool seen = false;
+    for (auto& t : take) seen |= (t.s == it->s);
+    if (!seen) {
+      take.push_back(*it);
+      it = srv->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  if (n_blocks) *n_blocks = (int32_t)take.size();
+  if (take.empty()) return RX_OK;
+  std::vector<Job> jobs(take.size());
+  InFlight f;
+  for (size_t i = 0; i < take.size(); ++i) {
+    rx_stream* s = take[i].s;
+    std::vector<Block> blks;
+    cut_blocks(s, s->lines_seen, take[i].lines, blks);
+    if (blks.size() != 1) return fail(RX_E_ARG, "a served block must not straddle a window edge");
+    bool notready = false;
+    rx_status r = prepare_job(s, take[i].x, blks, 0, 1, jobs[i], notready);
+    if (r != RX_OK) return r;
+    s->lines_seen += take[i].lines;
+    s->cnt.lines_pushed += take[i].lines;
+    f.items.push_back({s, take[i].tag});
+  }
+  rx_status r = launch_jobs(jobs, srv->st);
+  if (r != RX_OK) return r;
+  if (srv->free_events.empty()) {
+    hipEvent_t e;
+    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    srv->free_events.push_back(e);
+  }
+  f.ev = srv->free_events.back();
+  srv->free_events.pop_back();
+  HIPC(hipEventRecord(f.ev, srv->st));
+  srv->inflight.push_back(std::move(f));
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_poll(rx_server* srv, uint64_t* tags, int32_t max_tags, int32_t* n_done, int32_t block) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  if (!n_done || (!tags && max_tags > 0)) return fail(RX_E_ARG, "bad output arguments");
+  HIPC(hipSetDevice(srv->dev));
+  std::lock_guard<std::mutex> lk(srv->mu);
+  int32_t n = 0;
+  while (!srv->inflight.empty()) {
+    InFlight& f = srv->inflight.front();
+    if ((int32_t)(n + f.items.size()) > max_tags) break;
+    if (block) {
+      HIPC(hipEventSynchronize(f.ev));
+    } else {
+      const hipError_t q = hipEventQuery(f.ev);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(RX_E_DEVICE, "hipEventQuery: %s", hipGetErrorString(q));
+    }
+    for (auto& it : f.items) tags[n++] = it.second;
+    srv->free_events.push_back(f.ev);
+    srv->inflight.pop_front();
+  }
+  *n_done = n;
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_sync(rx_server* srv) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  HIPC(hipSetDevice(srv->dev));
+  HIPC(hipStreamSynchronize(srv->st));
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_queued(rx_server* srv, int32_t* queued, int32_t* inflight, size_t* used_bytes) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (queued) *queued = (int32_t)srv->queue.size();
+  if (inflight) {
+    int32_t c = 0;
+    for (auto& f : srv->inflight) c += (int32_t)f.items.size();
+    *inflight = c;
+  }
+  if (used_bytes) *used_bytes = srv->used;
+  return RX_OK;
+}

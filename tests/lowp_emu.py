@@ -1,0 +1,57 @@
+"""Host emulation of the low-precision whitening arithmetic (test support).
+
+Reproduces, in numpy, what the whitening kernel computes for the 8-value
+operand formats: FP32 centring with the mean split into hi + lo FP32 parts,
+power-of-two band scales 2^-e_k (e_k = floor(log2 sigma_k)), row scales 2^f_i
+(row maximum in [2^top, 2^(top+1))), round-to-nearest-even into BF16 / FP16 /
+OCP FP8 E4M3 (saturating at 448), exact products, FP64 sums.  It checks the
+kernel's quantisation and scaling, not the method: its inputs (W, mean,
+covariance) come from the library under test."""
+import numpy as np
+
+
+def q_bf16(x):
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def q_f16(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
+def q_e4m3(x):
+    x = np.asarray(x, dtype=np.float32).astype(np.float64)
+    s = np.sign(x)
+    a = np.abs(x)
+    out = np.empty_like(a)
+    sub = a < 2.0 ** -6
+    out[sub] = np.rint(a[sub] * 512.0) / 512.0
+    n = ~sub
+    e = np.floor(np.log2(np.where(n, a, 1.0)))
+    m = np.rint(np.where(n, a, 1.0) / 2.0 ** e * 8.0) / 8.0
+    out[n] = (m * 2.0 ** e)[n]
+    return s * np.minimum(out, 448.0)
+
+
+QUANT = {"bf16": (q_bf16, 14), "fp16": (q_f16, 14), "fp8": (q_e4m3, 7)}
+
+
+def emulate_scores(px, mean, cov_r, w, fmt):
+    """Scores the whitening kernel produces for format fmt, given the FP64
+    mean, regularised covariance (for the band scales) and whitener W."""
+    q, top = QUANT[fmt]
+    v = np.diag(cov_r)
+    sc = 1.0 / np.sqrt(v)
+    e = np.frexp(1.0 / sc)[1] - 1                       # floor(log2 sigma_k)
+    wt = np.ldexp(w, e[None, :])
+    m = np.abs(wt).max(axis=1)
+    f = np.where(m > 0, np.frexp(np.where(m > 0, m, 1.0))[1] - 1 - top, 0)
+    wq = q(np.ldexp(w, e[None, :] - f[:, None]).astype(np.float32))
+    mhi = mean.astype(np.float32)
+    mlo = (mean - mhi.astype(np.float64)).astype(np.float32)
+    d = (px.astype(np.float32) - mhi[None, :]) - mlo[None, :]
+    dq = q((d * np.ldexp(np.float32(1.0), -e)[None, :].astype(np.float32)).astype(np.float32))
+    y = (dq @ wq.T) * np.ldexp(1.0, f)[None, :]
+    return (y * y).sum(axis=1)

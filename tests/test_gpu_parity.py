@@ -1,0 +1,294 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (rel_err = |d_gpu - d_ref| / max(d_ref, 1e-3 B)), fixed before the
+first GPU run:
+  FP64 path            max 1e-9, p99 1e-11   (stress cube: 1e-7 / 1e-9)
+  FP32 path            max 1e-3, p99 1e-4
+  BF16 SYRK + BF16 whitening with the 1e-6 ridge: max 5e-2, p99 1e-2
+  FP16 / FP8 whitening: reported only (their errors are shown, not bounded)
+Masks must agree bit for bit wherever the oracle score is farther than the
+tolerance from the threshold (twice that in relative mode)."""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_mask, assert_scores, err_summary, oracle_stream_scores, say
+from oracle import rx as orx
+from paper_2602_13509_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-9, 1e-11), "fp32": (1e-3, 1e-4), "bf16": (5e-2, 1e-2)}
+
+
+@pytest.fixture(scope="module")
+def rxm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_13509_amd import rx
+    return rx
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_stream(rxm, cube, prec_s, prec_w, pushes=None, device_input=True, **cfgkw):
+    B, S = cube.shape[1], cube.shape[2]
+    cfg = rxm.make_config(B, S, in_dtype=cube.dtype, syrk=prec_s, whiten=prec_w, **cfgkw)
+    st = rxm.RxStream(cfg)
+    if pushes is None:
+        pushes = [cube.shape[0]]
+    l0 = 0
+    for n in pushes:
+        part = cube[l0:l0 + n]
+        st.rx_push_lines(dev(part) if device_input else np.ascontiguousarray(part))
+        l0 += n
+    st.rx_sync(allow=(rxm.RX_E_SINGULAR,))
+    return st
+
+
+# ---------------------------------------------------------------------------- golden exact rationals
+def test_golden_exact_rationals_fp64_path(rxm):
+    path = os.path.join(os.path.dirname(__file__), "golden", "tiny_exact.json")
+    for c in json.load(open(path)):
+        cube = np.array(c["cube"], dtype=np.uint16)
+        ref = np.array([float(Fraction(s)) for s in c["scores"]])
+        rn, rd = c["ridge_rel"]
+        say(f"golden B={c['bands']} S={c['samples']} L={c['lines']} ddof={c['ddof']}")
+        st = run_stream(rxm, cube, "fp64", "fp64", ddof=c["ddof"], ridge_rel=rn / rd)
+        got = st.scores_host(f64=True)
+        assert_scores(got, ref, c["bands"], 1e-9, 1e-9, "golden fp64")
+
+
+# ---------------------------------------------------------------------------- Gaussian cube, FP64
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gauss_cube_fp64_scores_and_topk(rxm, seed):
+    g = synth.gauss_cube(seed)
+    say(f"gauss seed={seed} 64x128x32 f64")
+    ref = orx.rx_batch(g.cube)
+    st = run_stream(rxm, g.cube, "fp64", "fp64")
+    m = st.mask_host(0.0, rxm.RX_THR_TOPK, 5)
+    assert np.array_equal(np.flatnonzero(m), g.anomalies)
+    got = st.scores_host(f64=True)
+    assert_scores(got, ref, 32, *TOL["fp64"], label="gauss fp64")
+    assert abs(got.mean() - 32) < 1e-8
+
+
+def test_gauss_cube_mixed_paths(rxm):
+    g = synth.gauss_cube(3)
+    ref = orx.rx_batch(g.cube)
+    for p in ("fp32", "bf16"):
+        st = run_stream(rxm, g.cube, p, p)
+        m = st.mask_host(0.0, rxm.RX_THR_TOPK, 5)      # the mask does not consume the scores
+        assert np.array_equal(np.flatnonzero(m), g.anomalies)
+        got = st.scores_host()
+        say(f"gauss {p}: max/p99 rel {err_summary(got, ref, 32)}")
+        if p == "fp32":
+            assert_scores(got, ref, 32, *TOL["fp32"], label="gauss fp32")
+
+
+# ---------------------------------------------------------------------------- sensor cube, several tiles + ragged tail
+@pytest.mark.parametrize("samples", [200, 203])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_sensor_cube_blocks(rxm, prec, samples):
+    B = 270
+    cube = synth.sensor_cube(11, lines=90, samples=samples, bands=B).cube
+    rho = 1e-6 if prec == "bf16" else 0.0
+    say(f"sensor 90x{samples}x{B} u16 prec={prec} block_lines=40 rho={rho}")
+    ref, _ = oracle_stream_scores(cube, B, samples, block_lines=40, rho=rho)
+    st = run_stream(rxm, cube, prec, prec, block_lines=40, ridge_rel=rho)
+    got = st.scores_host(f64=(prec == "fp64"))
+    assert_scores(got, ref, B, *TOL[prec], label=f"sensor {prec} S={samples}")
+
+
+def test_sensor_cube_host_input_and_push_split(rxm):
+    B, S = 120, 96
+    cube = synth.sensor_cube(12, lines=60, samples=S, bands=B).cube
+    pushes = [7, 13, 40]
+    ref, _ = oracle_stream_scores(cube, B, S, pushes=pushes)
+    st = run_stream(rxm, cube, "fp64", "fp64", pushes=pushes, device_input=False)
+    assert_scores(st.scores_host(f64=True), ref, B, *TOL["fp64"], label="host input, pushes 7/13/40")
+
+
+def test_window_reset_matches_independent_cubes(rxm):
+    B, S = 64, 80
+    cube = synth.sensor_cube(13, lines=75, samples=S, bands=B).cube
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=10, window_lines=25)
+    st = run_stream(rxm, cube, "fp64", "fp64", block_lines=10, window_lines=25)
+    assert_scores(st.scores_host(f64=True), ref, B, *TOL["fp64"], label="window 25, blocks 10")
+
+
+@pytest.mark.parametrize("B", [1, 2, 17, 31, 64, 65, 300])
+def test_band_counts(rxm, B):
+    S = 72
+    cube = synth.sensor_cube(14, lines=12, samples=S, bands=B).cube
+    ref, _ = oracle_stream_scores(cube, B, S)
+    st = run_stream(rxm, cube, "fp64", "fp64")
+    assert_scores(st.scores_host(f64=True), ref, B, *TOL["fp64"], label=f"B={B} fp64")
+    st2 = run_stream(rxm, cube, "fp32", "fp32")
+    assert_scores(st2.scores_host(), ref, B, *TOL["fp32"], label=f"B={B} fp32")
+
+
+# ---------------------------------------------------------------------------- statistics and factor hooks
+def test_stats_match_exact_integer_covariance(rxm):
+    B, S = 270, 128
+    cube = synth.sensor_cube(15, lines=30, samples=S, bands=B).cube
+    px = orx.pixels(cube)
+    mu, cov = orx.stats(px)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 2e-2)):
+        st = run_stream(rxm, cube, prec, prec, block_lines=8, ridge_rel=1e-6 if prec == "bf16" else 0.0)
+        n, m, c = st.rx_get_stats()
+        assert n == px.shape[0]
+        assert np.max(np.abs(m - mu)) <= 1e-12 * np.abs(mu).max()
+        err = np.max(np.abs(c - cov)) / np.abs(cov).max()
+        say(f"  stats {prec}: max |cov err| / max|cov| = {err:.3e}")
+        assert err <= tol
+
+
+def test_whitener_inverts_regularised_covariance(rxm):
+    B, S = 40, 64
+    cube = synth.sensor_cube(16, lines=20, samples=S, bands=B).cube
+    st = run_stream(rxm, cube, "fp64", "fp64", ridge_rel=1e-3)
+    w = st.rx_get_whitener()
+    assert np.all(np.triu(w, 1) == 0)
+    _, mu, cov = st.rx_get_stats()
+    cov_r = orx.regularise(cov, 1e-3)
+    # W Sigma_r W^T = I  (whitened identity)
+    assert np.max(np.abs(w @ cov_r @ w.T - np.eye(B))) <= 1e-10
+
+
+def test_set_stats_roundtrip(rxm):
+    B, S = 32, 64
+    a = synth.sensor_cube(17, lines=20, samples=S, bands=B).cube
+    b = synth.sensor_cube(18, lines=5, samples=S, bands=B).cube
+    s1 = run_stream(rxm, a, "fp64", "fp64")
+    n, m, c = s1.rx_get_stats()
+    s1.scores_host(f64=True)
+    s1.rx_push_lines(dev(b))
+    want = s1.scores_host(f64=True)
+    s2 = rxm.RxStream(rxm.make_config(B, S, syrk="fp64", whiten="fp64"))
+    s2.rx_set_stats(n, m, c)
+    s2.rx_push_lines(dev(b))
+    got = s2.scores_host(f64=True)
+    assert_scores(got, want, B, 1e-9, 1e-11, "restored stream")
+
+
+# ---------------------------------------------------------------------------- degenerate cases
+def test_not_ready_then_ready(rxm):
+    B, S = 16, 4
+    cube = synth.sensor_cube(19, lines=10, samples=S, bands=B).cube
+    cfg = rxm.make_config(B, S, syrk="fp64", whiten="fp64")
+    st = rxm.RxStream(cfg)
+    r = st.rx_push_lines(dev(cube[:2]))               # N = 8 <= B
+    assert r == rxm.RX_E_NOTREADY
+    got = st.scores_host(f64=True)
+    assert np.all(np.isnan(got))
+    assert st.rx_push_lines(dev(cube[2:])) == rxm.RX_OK   # N = 40 > B
+    ref, _ = oracle_stream_scores(cube, B, S, pushes=[2, 8])
+    assert_scores(st.scores_host(f64=True), ref[8:], B, 1e-9, 1e-11, "after not-ready")
+
+
+def test_constant_band_is_singular_without_ridge(rxm):
+    B, S = 8, 32
+    cube = synth.sensor_cube(20, lines=6, samples=S, bands=B).cube
+    cube[:, 3, :] = 1000
+    st = run_stream(rxm, cube, "fp64", "fp64")
+    assert st.rx_get_counters().singular_blocks == 1
+    assert np.all(np.isnan(st.scores_host(f64=True)))
+    st2 = run_stream(rxm, cube, "fp64", "fp64", ridge_rel=1e-3)
+    ref, _ = oracle_stream_scores(cube, B, S, rho=1e-3)
+    assert_scores(st2.scores_host(f64=True), ref, B, 1e-9, 1e-11, "constant band + ridge")
+
+
+def test_sync_reports_singular(rxm):
+    B, S = 8, 32
+    cube = synth.sensor_cube(21, lines=6, samples=S, bands=B).cube
+    cube[:, 0, :] = 7
+    cfg = rxm.make_config(B, S, syrk="fp64", whiten="fp64")
+    st = rxm.RxStream(cfg)
+    st.rx_push_lines(dev(cube))
+    assert st.rx_sync(allow=(rxm.RX_E_SINGULAR,)) == rxm.RX_E_SINGULAR
+    assert st.rx_sync() == rxm.RX_OK          # sticky error is cleared
+
+
+# ---------------------------------------------------------------------------- masks
+def test_masks_abs_rel_topk(rxm):
+    B, S = 270, 128
+    cube = synth.sensor_cube(22, lines=40, samples=S, bands=B).cube
+    ref, _ = oracle_stream_scores(cube, B, S)
+    for prec in ("fp64", "fp32"):
+        st = run_stream(rxm, cube, prec, prec)
+        tol = TOL[prec][0]
+        tau = float(np.quantile(ref, 1 - 5e-4))
+        assert_mask(st.mask_host(tau, rxm.RX_THR_ABS), ref, tau, tol, B, f"{prec} abs")
+        assert_mask(st.mask_host(0.110, rxm.RX_THR_REL_MAX), ref, 0.110 * ref.max(), 2 * tol, B, f"{prec} rel")
+        k = 7
+        m = st.mask_host(0.0, rxm.RX_THR_TOPK, k)
+        assert m.sum() == k
+        order = np.lexsort((np.arange(ref.size), -ref))
+        if ref[order[k - 1]] - ref[order[k]] > 2 * tol * ref[order[k - 1]]:
+            assert np.array_equal(np.flatnonzero(m), np.sort(order[:k]))
+
+
+def test_topk_ties_go_to_lower_index(rxm):
+    # identical pixels produce exactly tied scores on the GPU
+    B, S = 4, 64
+    base = synth.sensor_cube(23, lines=3, samples=S, bands=B).cube
+    base[1, :, 10] = base[0, :, 5] = base[2, :, 60] = np.array([4000, 10, 4000, 10], dtype=np.uint16)
+    st = run_stream(rxm, base, "fp64", "fp64")
+    m = st.mask_host(0.0, rxm.RX_THR_TOPK, 2)
+    d = st.scores_host(f64=True)
+    tied = np.flatnonzero(d == d.max())
+    assert tied.size == 3
+    assert np.array_equal(np.flatnonzero(m), tied[:2])
+
+
+# ---------------------------------------------------------------------------- low precision on the stress cube
+def test_stress_cube_precisions(rxm):
+    B, S = 300, 128
+    sc = synth.stress_cube(3, lines=40, samples=S, bands=B)
+    ref, _ = oracle_stream_scores(sc.cube, B, S)
+    st = run_stream(rxm, sc.cube, "fp64", "fp64")
+    assert_scores(st.scores_host(f64=True), ref, B, 1e-7, 1e-9, "stress fp64")
+    for w in ("fp16", "fp8"):
+        st = run_stream(rxm, sc.cube, "fp64", w)
+        got = st.scores_host()
+        mx, p99 = err_summary(got, ref, B)
+        say(f"  stress fp64 stats + {w} whitening: max rel {mx:.3e}, p99 rel {p99:.3e} (reported)")
+        assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8"])
+@pytest.mark.parametrize("kind", ["sensor", "stress"])
+def test_lowp_whitening_matches_host_emulation(rxm, fmt, kind):
+    # The kernel's quantisation (band/row power-of-two scales, RNE, FP8
+    # saturation) and matrix-core accumulation against a numpy emulation of
+    # the same arithmetic built from the library's own FP64 W and statistics.
+    from lowp_emu import emulate_scores
+    if kind == "sensor":
+        B, S = 270, 128
+        cube = synth.sensor_cube(25, lines=20, samples=S, bands=B).cube
+    else:
+        B, S = 300, 128
+        cube = synth.stress_cube(4, lines=20, samples=S, bands=B).cube
+    st = run_stream(rxm, cube, "fp64", fmt)
+    got = st.scores_host()
+    w = st.rx_get_whitener()
+    n, mean, cov = st.rx_get_stats()
+    emu = emulate_scores(orx.pixels(cube), mean, cov, w, fmt)
+    e = np.abs(got - emu) / np.maximum(emu, 1e-3 * B)
+    say(f"  {kind} {fmt}: kernel vs emulation max rel {e.max():.3e}")
+    assert e.max() <= 1e-4          # FP32 accumulation order only (~3e-6 measured on the host)
+
+
+def test_determinism_bitwise(rxm):
+    B, S = 270, 128
+    cube = synth.sensor_cube(24, lines=30, samples=S, bands=B).cube
+    a = run_stream(rxm, cube, "bf16", "bf16", block_lines=10, ridge_rel=1e-6).scores_host()
+    b = run_stream(rxm, cube, "bf16", "bf16", block_lines=10, ridge_rel=1e-6).scores_host()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
