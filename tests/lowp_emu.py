@@ -38,9 +38,11 @@ def q_e4m3(x):
 QUANT = {"bf16": (q_bf16, 14), "fp16": (q_f16, 14), "fp8": (q_e4m3, 7)}
 
 
-def emulate_scores(px, mean, cov_r, w, fmt):
+def emulate_scores(px, mean, cov_r, w, fmt, with_scale=False):
     """Scores the whitening kernel produces for format fmt, given the FP64
-    mean, regularised covariance (for the band scales) and whitener W."""
+    mean, regularised covariance (for the band scales) and whitener W.
+    with_scale: also return, per pixel, sum_i |y_i| * sum_j |Wq_ij dq_j| * 2^f_i,
+    the magnitude that FP32 accumulation rounding is proportional to."""
     q, top = QUANT[fmt]
     v = np.diag(cov_r)
     sc = 1.0 / np.sqrt(v)
@@ -54,4 +56,8 @@ def emulate_scores(px, mean, cov_r, w, fmt):
     d = (px.astype(np.float32) - mhi[None, :]) - mlo[None, :]
     dq = q((d * np.ldexp(np.float32(1.0), -e)[None, :].astype(np.float32)).astype(np.float32))
     y = (dq @ wq.T) * np.ldexp(1.0, f)[None, :]
-    return (y * y).sum(axis=1)
+    delta = (y * y).sum(axis=1)
+    if not with_scale:
+        return delta
+    mag = (np.abs(dq) @ np.abs(wq).T) * np.ldexp(1.0, f)[None, :]
+    return delta, (np.abs(y) * mag).sum(axis=1)

@@ -280,10 +280,16 @@ def test_lowp_whitening_matches_host_emulation(rxm, fmt, kind):
     got = st.scores_host()
     w = st.rx_get_whitener()
     n, mean, cov = st.rx_get_stats()
-    emu = emulate_scores(orx.pixels(cube), mean, cov, w, fmt)
-    e = np.abs(got - emu) / np.maximum(emu, 1e-3 * B)
-    say(f"  {kind} {fmt}: kernel vs emulation max rel {e.max():.3e}")
-    assert e.max() <= 1e-4          # FP32 accumulation order only (~3e-6 measured on the host)
+    emu, scale = emulate_scores(orx.pixels(cube), mean, cov, w, fmt, with_scale=True)
+    # Allowed: FP32 accumulation rounding, |d delta| <= 2 sum_i |y_i| |dy_i| with
+    # |dy_i| <= c u32 sum_j |w_ij d_j|; c = 2^10 leaves room for the matrix
+    # cores' internal summation order and stays far below one step of any of
+    # the operand formats (2^-8 .. 2^-3 relative), so a quantisation mistake fails.
+    bound = 2.0 * 1024 * 2.0 ** -24 * scale + 1e-6 * np.maximum(emu, 1e-3 * B)
+    e = np.abs(got - emu)
+    say(f"  {kind} {fmt}: kernel vs emulation max |diff|/bound {np.max(e / bound):.3e}, "
+        f"max rel {np.max(e / np.maximum(emu, 1e-3 * B)):.3e}")
+    assert np.all(e <= bound)
 
 
 def test_determinism_bitwise(rxm):
