@@ -3,13 +3,11 @@
 // Sigma^{-1}; it is applied as delta = |W (x - mu)|^2 with W lower
 // triangular and W^T W = (Sigma + lambda I)^{-1}.
 //
-// One workgroup per block snapshot:
+// One 512-thread workgroup per block snapshot:
 //   Sigma = M2 / (N - ddof);  lambda = rho * tr(Sigma) / B;  Sigma_r = Sigma + lambda I
 //   equilibration R = S Sigma_r S with S = diag(Sigma_r,kk^{-1/2})  (unit diagonal)
-//   R = L L^T, W = L^{-1} S, built block-row by block-row (16 rows at a time,
-//   bordering): with W_K = L_K^{-1} known for the leading K rows,
-//     L21 = A21 W_K^T,  L22 L22^T = A22 - L21 L21^T,  Y = L22^{-1},
-//     new rows of L^{-1}:  [ -Y L21 W_K , Y ].
+//   R = L L^T and W = L^{-1} S in one right-looking sweep over 16x16 tiles
+//   held in registers, FP64 matrix-core products (details below).
 //   A non-positive pivot flags the block singular (its scores become NaN).
 // The whitening operand in the whitening precision is then formed with
 // power-of-two scales: input band scale 2^-e_k (e_k = floor(log2 sigma_k))
@@ -19,25 +17,38 @@
 namespace rxk {
 
 constexpr int MAXBP = 16 * MAXT;
+constexpr int FNW = 8;                  // waves per factor workgroup (2 per SIMD: 256 registers each)
+constexpr int FNT = 64 * FNW;           // threads per factor workgroup
+// lower tiles per wave: a template argument sized to the band count; up to
+// 20 tiles (B <= 272) the tiles and the step's temporaries fit in registers
+constexpr int ftpw_for(int T) { return (T * (T + 1) / 2 + FNW - 1) / FNW; }
+constexpr int FTS = 16 * 17;            // LDS tile: 16 rows, pitch 17 doubles (bank-conflict free)
 
-template <int WP>
-__global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  int2 v = __builtin_bit_cast(int2, x);
+  v.x = __builtin_amdgcn_readlane(v.x, l);
+  v.y = __builtin_amdgcn_readlane(v.y, l);
+  return __builtin_bit_cast(double, v);
+}
+
+template <int WP, int FTPW>
+__global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
   int b;
   const int bi = find_batch(ls, blockIdx.x, b);
   const BatchDesc& d = ls.d[bi];
   const int B = d.B, Bp = d.Bp;
   const int64_t bp2 = (int64_t)Bp * Bp;
-  double* R = d.m2_snap + b * bp2;
+  const double* R = d.m2_snap + b * bp2;
   double* W = d.w64 + b * bp2;
-  double* WT = d.wt64 + b * bp2;
-  __shared__ double A[16 * MAXBP];   // A21, then X = Y L21
-  __shared__ double L[16 * MAXBP];   // L21
-  __shared__ double sc[MAXBP];       // equilibration scale
+  __shared__ double lcol[MAXT * FTS];   // pivot column: R_ik, then L_ik
+  __shared__ double prow[MAXT * FTS];   // pivot row: E_kj, then W_kj; Y at k
+  __shared__ double ybuf[FTS];          // Y = L_kk^{-1}
+  __shared__ double sc[MAXBP];          // equilibration scale
   __shared__ double T22[16][17];
-  __shared__ double Y[16][17];
-  __shared__ double red[NT / 64];
+  __shared__ double red[FNW];
   __shared__ int flag;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const double N = d.n_snap[b];
 
   if (d.rho == 0.0 && N <= (double)B) {       // window too small: Sigma is singular
@@ -49,14 +60,14 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
 
   // ---- trace and ridge
   double tr = 0.0;
-  for (int k = tid; k < B; k += NT) tr += R[(int64_t)k * Bp + k];
+  for (int k = tid; k < B; k += FNT) tr += R[(int64_t)k * Bp + k];
   tr = wave_sum(tr);
   if (lane == 0) red[wv] = tr;
   __syncthreads();
   tr = 0.0;
-  for (int i = 0; i < NT / 64; ++i) tr += red[i];
+  for (int i = 0; i < FNW; ++i) tr += red[i];
   const double lam = d.rho * (tr / den) / (double)B;
-  for (int k = tid; k < Bp; k += NT) {
+  for (int k = tid; k < Bp; k += FNT) {
     double v = 1.0;
     if (k < B) {
       v = R[(int64_t)k * Bp + k] / den + lam;
@@ -69,53 +80,70 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
     if (tid == 0) { d.status[b] = 1; atomicAdd(d.nsing, 1u); }
     return;
   }
-  // ---- equilibrate in place (lower triangle); padding becomes identity
-  for (int64_t idx = tid; idx < bp2; idx += NT) {
-    const int i = (int)(idx / Bp), j = (int)(idx % Bp);
-    if (j > i) continue;
-    double v;
-    if (i < B && j < B) v = (i == j) ? (R[idx] / den + lam) * sc[i] * sc[i] : (R[idx] / den) * sc[i] * sc[j];
-    else v = (i == j) ? 1.0 : 0.0;
-    R[idx] = v;
-  }
-  __syncthreads();
 
-  // ---- bordered blocked inverse Cholesky
-  for (int K = 0; K < Bp; K += 16) {
-    for (int idx = tid; idx < 16 * K; idx += NT) {
-      const int r = idx / K, t = idx % K;
-      A[r * MAXBP + t] = R[(int64_t)(K + r) * Bp + t];
-    }
-    {
-      const int r = tid >> 4, q = tid & 15;
-      T22[r][q] = (q <= r) ? R[(int64_t)(K + r) * Bp + K + q] : R[(int64_t)(K + q) * Bp + K + r];
-    }
-    __syncthreads();
-    // L21 = A21 W_K^T  (column c of L21 needs row c of W_K, i.e. column c of WT)
-    for (int c = tid; c < K; c += NT) {
-      double acc[16];
+  // ---- one right-looking sweep over 16x16 tiles held in registers:
+  // every lower tile (i, j) of R lives in one wave (cyclic ownership).  At
+  // step k the diagonal tile is factored (L_kk, Y = L_kk^{-1}); the pivot
+  // column becomes L_ik = R_ik Y^T; the pivot row of the eliminated identity
+  // becomes final rows of W = L^{-1}: W_kj = Y E_kj (W_kk = Y); every tile
+  // below row k is then updated with one 16x16x16 product:
+  //   j > k: R_ij -= L_ik L_jk^T     j == k: E_ik = -L_ik Y     j < k: E_ij -= L_ik W_kj
+  // so each tile holds R, then L (pivot column), then E, then W.
+  const int T = Bp / 16, ntiles = T * (T + 1) / 2;
+  const int lr = lane & 15, lg = lane >> 4;
+  // LDS tiles are row-major with pitch 17: element (r, c) at r * 17 + c.
+  // offA: this lane's element of an A-operand (or transposed B) read, (lr, 4q + lg);
+  // offB: of a B-operand read / accumulator write, (lg + 4q, lr).  Per-step reads
+  // use these with immediate offsets (4q, 68q).
+  const int offA0 = lr * 17 + lg, offB0 = lg * 17 + lr;
+  const double rden = 1.0 / den;
+  f64x4 tl[FTPW];
+  int ti[FTPW], tj[FTPW];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-      for (int t = 0; t <= c; ++t) {
-        const double w = WT[(int64_t)t * Bp + c];
+  for (int s = 0; s < FTPW; ++s) {
+    const int t = s * FNW + wv;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    ti[s] = __builtin_amdgcn_readfirstlane((t < ntiles) ? i : -1);
+    tj[s] = __builtin_amdgcn_readfirstlane((t < ntiles) ? t - i * (i + 1) / 2 : -1);
+    tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+    if (ti[s] >= 0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] += A[r * MAXBP + t] * w;
+      for (int r = 0; r < 4; ++r) {
+        // branch-free: every lane loads a valid address, padding is selected away
+        const int row = 16 * ti[s] + lg + 4 * r, col = 16 * tj[s] + lr;
+        const bool in = (row < B) && (col < B);
+        const int hi = in ? (row >= col ? row : col) : 0, lo = in ? (row >= col ? col : row) : 0;
+        double v = R[(int64_t)hi * Bp + lo] * rden + ((row == col) ? lam : 0.0);
+        v *= sc[row] * sc[col];
+        v = in ? v : ((row == col) ? 1.0 : 0.0);
+        tl[s][r] = v;
       }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int k = 0; k < T; ++k) {
+    int offA = offA0, offB = offB0;
+    asm volatile("" : "+v"(offA), "+v"(offB));   // keep derived addresses inside the step
+    // stage the tiles this step reads from other waves
 #pragma unroll
-      for (int r = 0; r < 16; ++r) L[r * MAXBP + c] = acc[r];
+    for (int s = 0; s < FTPW; ++s) {
+      double* dst = nullptr;
+      if (ti[s] == k && tj[s] == k) dst = &T22[0][0];
+      else if (tj[s] == k && ti[s] > k) dst = lcol + ti[s] * FTS;
+      else if (ti[s] == k && tj[s] >= 0 && tj[s] < k) dst = prow + tj[s] * FTS;
+      if (dst) {
+        double* p = dst + offB;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    {
-      const int r = tid >> 4, q = tid & 15;
-      double s = T22[r][q];
-      for (int c = 0; c < K; ++c) s -= L[r * MAXBP + c] * L[q * MAXBP + c];
-      __syncthreads();
-      T22[r][q] = s;
-    }
-    __syncthreads();
-    // 16x16 Cholesky in wave 0: lane = (row i, column group cg of 4)
+    // 16x16 Cholesky of the diagonal tile in wave 0: lane = (row i, column group cg of 4)
     if (wv == 0) {
-      const int i = lane & 15, cg = lane >> 4;
+      int i = lane & 15, cg = lane >> 4;
+      asm volatile("" : "+v"(i), "+v"(cg));    // shuffle addresses are formed per step, not hoisted
       double v[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = T22[i][4 * cg + e];
@@ -123,19 +151,20 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int je = j & 3, jg = j >> 2;
-        const double piv = __shfl(v[je], j + 16 * jg, 64);
+        const double piv = readlane_d(v[je], j + 16 * jg);
         bad |= !(piv > 0.0);
-        const double dd = sqrt(piv);
-        const double lij = __shfl(v[je], i + 16 * jg, 64) / dd;
+        const double rd = 1.0 / sqrt(piv);
+        const double lij = __shfl(v[je], i + 16 * jg, 64) * rd;
         double lkj[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) / dd;
+        for (int e = 0; e < 4; ++e) lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int k = 4 * cg + e;
-          if (k > j && i >= k) v[e] -= lij * lkj[e];
+          const int kk = 4 * cg + e;
+          if (kk > j && i >= kk) v[e] -= lij * lkj[e];
         }
-        if (cg == jg) v[je] = (i > j) ? lij : (i == j ? dd : 0.0);
+        if (cg == jg) v[je] = (i > j) ? lij : (i == j ? piv * rd : 0.0);
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) T22[i][4 * cg + e] = v[e];
@@ -143,55 +172,70 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
     }
     __syncthreads();
     if (flag) break;
-    if (tid < 16) {                 // Y = L22^{-1}, one column per thread
+    if (tid < 16) {                 // Y = L_kk^{-1}, one column per lane, built in place in LDS
       const int q = tid;
-      double y[16];
-#pragma unroll
+#pragma unroll 1
       for (int i = 0; i < 16; ++i) {
-        double s = (i == q) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= T22[i][k] * y[k];
-        y[i] = (i >= q) ? s / T22[i][i] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) Y[i][q] = y[i];
-    }
-    __syncthreads();
-    // X = Y L21 (overwrites A21)
-    for (int c = tid; c < K; c += NT) {
-      double l[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) l[q] = L[q * MAXBP + c];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double x = 0.0;
-#pragma unroll
-        for (int q = 0; q <= r; ++q) x += Y[r][q] * l[q];
-        A[r * MAXBP + c] = x;
+        double s2 = (i == q) ? 1.0 : 0.0;
+        for (int m = 0; m < i; ++m) s2 -= T22[i][m] * ybuf[m * 17 + q];
+        ybuf[i * 17 + q] = (i >= q) ? s2 / T22[i][i] : 0.0;
       }
     }
     __syncthreads();
-    // new rows K..K+15 of L^{-1} (full width) and their transpose
-    for (int t = tid; t < Bp; t += NT) {
-      double acc[16];
+    // pivot column L_ik = R_ik Y^T, pivot row W_kj = Y E_kj, W_kk = Y
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-      if (t < K) {
-        // all lanes of a wave walk the same c, so W row c is read coalesced
-        for (int c = t & ~63; c < K; ++c) {
-          const double w = (c >= t) ? W[(int64_t)c * Bp + t] : 0.0;
+    for (int s = 0; s < FTPW; ++s) {
+      if (tj[s] == k && ti[s] > k) {
+        double* lc = lcol + ti[s] * FTS;
+        const double* la = lc + offA;
+        const double* yb = ybuf + offA;
+        tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int r = 0; r < 16; ++r) acc[r] -= A[r * MAXBP + c] * w;
+        for (int q4 = 0; q4 < 4; ++q4)
+          tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[4 * q4], yb[4 * q4], tl[s], 0, 0, 0);
+        double* p = lc + offB;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+      } else if (ti[s] == k && tj[s] >= 0 && tj[s] < k) {
+        double* pr = prow + tj[s] * FTS;
+        const double* ya = ybuf + offA;
+        const double* pb = pr + offB;
+        tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
+        double* p = pr + offB;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+      } else if (ti[s] == k && tj[s] == k) {
+        const double* yb = ybuf + offB;
+        double* p = prow + k * FTS + offB;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          tl[s][r] = yb[68 * r];
+          p[68 * r] = tl[s][r];
         }
-      } else if (t < K + 16) {
-        const int q = t - K;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = (q <= r) ? Y[r][q] : 0.0;
       }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    // update every tile below row k
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        W[(int64_t)(K + r) * Bp + t] = acc[r];
-        WT[(int64_t)t * Bp + K + r] = acc[r];
+    for (int s = 0; s < FTPW; ++s) {
+      if (ti[s] > k) {
+        const double* la = lcol + ti[s] * FTS + offA;
+        if (tj[s] == k) tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        if (tj[s] > k) {
+          const double* lb = lcol + tj[s] * FTS + offA;
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4)
+            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], lb[4 * q4], tl[s], 0, 0, 0);
+        } else {
+          const double* pb = prow + tj[s] * FTS + offB;
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4)
+            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -200,22 +244,32 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
     if (tid == 0) { d.status[b] = 1; atomicAdd(d.nsing, 1u); }
     return;
   }
-
-  // ---- W = L^{-1} S (FP64), padding rows/columns zeroed
-  for (int64_t idx = tid; idx < bp2; idx += NT) {
+  // ---- W = L^{-1} S (FP64, row-major), zero above the diagonal and in the padding
+#pragma unroll
+  for (int s = 0; s < FTPW; ++s) {
+    if (ti[s] >= 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti[s] + lg + 4 * r, col = 16 * tj[s] + lr;
+        W[(int64_t)row * Bp + col] = (row < B && col < B && col <= row) ? tl[s][r] * sc[col] : 0.0;
+      }
+    }
+  }
+  for (int64_t idx = tid; idx < bp2; idx += FNT) {
     const int i = (int)(idx / Bp), j = (int)(idx % Bp);
-    W[idx] = (i < B && j < B && j <= i) ? W[idx] * sc[j] : 0.0;
+    if ((j >> 4) > (i >> 4)) W[idx] = 0.0;
   }
   __syncthreads();
+
 
   // ---- whitening operand in the whitening precision
   if constexpr (WP == P_F32) {
     float* wl = static_cast<float*>(d.wlp) + (int64_t)b * Bp * Bw;
-    for (int64_t idx = tid; idx < (int64_t)Bp * Bw; idx += NT) {
+    for (int64_t idx = tid; idx < (int64_t)Bp * Bw; idx += FNT) {
       const int i = (int)(idx / Bw), j = (int)(idx % Bw);
       wl[idx] = (j < Bp) ? (float)W[(int64_t)i * Bp + j] : 0.0f;
     }
-    for (int k = tid; k < Bp; k += NT) {
+    for (int k = tid; k < Bp; k += FNT) {
       d.iscale[(int64_t)b * Bp + k] = 1.0f;
       d.oscale[(int64_t)b * Bp + k] = 1.0f;
     }
@@ -225,13 +279,13 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
     constexpr int top = (WP == P_FP8) ? 7 : 14;     // row max lands in [2^top, 2^(top+1))
     __shared__ int ek[MAXBP];
     __shared__ int fi[MAXBP];
-    for (int k = tid; k < Bp; k += NT) {
+    for (int k = tid; k < Bp; k += FNT) {
       const int e = (k < B) ? ilogb(1.0 / sc[k]) : 0;   // 2^e <= sigma_k < 2^(e+1)
       ek[k] = e;
       d.iscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, -e);
     }
     __syncthreads();
-    for (int i = tid; i < Bp; i += NT) {
+    for (int i = tid; i < Bp; i += FNT) {
       double m = 0.0;
       for (int j = 0; j <= i && j < B; ++j) m = fmax(m, fabs(ldexp(W[(int64_t)i * Bp + j], ek[j])));
       const int f = (m > 0.0) ? ilogb(m) - top : 0;
@@ -239,7 +293,7 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
       d.oscale[(int64_t)b * Bp + i] = (float)ldexp(1.0, f);
     }
     __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)Bp * Bw; idx += NT) {
+    for (int64_t idx = tid; idx < (int64_t)Bp * Bw; idx += FNT) {
       const int i = (int)(idx / Bw), j = (int)(idx % Bw);
       float v = 0.0f;
       if (j < Bp) v = (float)ldexp(W[(int64_t)i * Bp + j], ek[j] - fi[i]);
@@ -251,16 +305,27 @@ __global__ void __launch_bounds__(NT) k_factor(LaunchSet ls, int Bw) {
 
 }  // namespace rxk
 
+template <int WP>
+static void launch_factor_t(const rxk::LaunchSet* ls, int wg, int Bw, hipStream_t st) {
+  using namespace rxk;
+  int T = 0;                                // the largest band-tile count of the launch sizes the tile array
+  for (int i = 0; i < ls->nb; ++i) T = T > ls->d[i].Bp / 16 ? T : ls->d[i].Bp / 16;
+  if (T <= 12) hipLaunchKernelGGL((k_factor<WP, ftpw_for(12)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
+  else if (T <= 17) hipLaunchKernelGGL((k_factor<WP, ftpw_for(17)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
+  else if (T <= 19) hipLaunchKernelGGL((k_factor<WP, ftpw_for(19)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
+  else hipLaunchKernelGGL((k_factor<WP, ftpw_for(MAXT)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
+}
+
 extern "C" hipError_t rxk_launch_factor(int wprec, const rxk::LaunchSet* ls, int wg, int Bw,
                                         hipStream_t st) {
   using namespace rxk;
   if (wg <= 0) return hipSuccess;
   switch (wprec) {
-    case P_F64: hipLaunchKernelGGL((k_factor<P_F64>), dim3(wg), dim3(NT), 0, st, *ls, Bw); break;
-    case P_F32: hipLaunchKernelGGL((k_factor<P_F32>), dim3(wg), dim3(NT), 0, st, *ls, Bw); break;
-    case P_BF16: hipLaunchKernelGGL((k_factor<P_BF16>), dim3(wg), dim3(NT), 0, st, *ls, Bw); break;
-    case P_F16: hipLaunchKernelGGL((k_factor<P_F16>), dim3(wg), dim3(NT), 0, st, *ls, Bw); break;
-    case P_FP8: hipLaunchKernelGGL((k_factor<P_FP8>), dim3(wg), dim3(NT), 0, st, *ls, Bw); break;
+    case P_F64: launch_factor_t<P_F64>(ls, wg, Bw, st); break;
+    case P_F32: launch_factor_t<P_F32>(ls, wg, Bw, st); break;
+    case P_BF16: launch_factor_t<P_BF16>(ls, wg, Bw, st); break;
+    case P_F16: launch_factor_t<P_F16>(ls, wg, Bw, st); break;
+    case P_FP8: launch_factor_t<P_FP8>(ls, wg, Bw, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

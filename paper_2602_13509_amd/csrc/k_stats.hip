@@ -9,10 +9,10 @@
 //   k_syrk   -- C = sum_p (x_p - c)(x_p - c)^T on matrix cores, lower 64x64
 //               super-tiles x split-K over pixel chunks, FP32 (or FP64)
 //               partials; diagonal super-tiles also emit exact raw band sums.
-//   k_merge  -- fixed-order FP64 reduction of the partials, exact shift
-//               correction M2_b = C - n e e^T (e = m_b - c), then the
-//               pairwise (Chan-Golub-LeVeque) update of the window
-//               (N, S1, M2), snapshotting the window after every block.
+//   k_merge_vec / k_merge_mat -- fixed-order FP64 reduction of the
+//               partials, exact shift correction M2_b = C - n e e^T
+//               (e = m_b - c), then the pairwise (Chan-Golub-LeVeque) update
+//               of the window (N, S1, M2), snapshotting it after every block.
 #include "rx_dev.h"
 
 namespace rxk {
@@ -148,19 +148,19 @@ __global__ void __launch_bounds__(NT) k_syrk(LaunchSet ls) {
     __syncthreads();
   }
 
-  // ---- write the partial super-tile (row-major 64x64)
+  // ---- write the partial scatter into the split's Bp x Bp matrix (lower part)
   const int64_t slot = (int64_t)b * d.ks + split;
   if (!skip) {
-    C* out = static_cast<C*>(d.part) + (slot * d.nsup + sup) * (SUP * SUP);
+    C* out = static_cast<C*>(d.part) + slot * d.Bp * d.Bp;
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int rr = 32 * wr + 16 * ti + M::out_row(lane >> 4, j);
-          const int cc = 32 * wc + 16 * tj + lr;
-          out[rr * SUP + cc] = acc[ti][tj][j];
+          const int gi = 64 * I + 32 * wr + 16 * ti + M::out_row(lane >> 4, j);
+          const int gj = 64 * J + 32 * wc + 16 * tj + lr;
+          if (gi < d.Bp && gj < d.Bp) out[(int64_t)gi * d.Bp + gj] = acc[ti][tj][j];
         }
   }
   // ---- raw band sums (diagonal super-tiles cover every band exactly once)
@@ -171,99 +171,94 @@ __global__ void __launch_bounds__(NT) k_syrk(LaunchSet ls) {
 }
 
 // ---------------------------------------------------------------------------- merge
-// One workgroup per lower super-tile; it walks the batch's blocks in order.
-template <typename PT>
-__global__ void __launch_bounds__(NT) k_merge(LaunchSet ls) {
-  int sup;
-  const int bi = find_batch(ls, blockIdx.x, sup);
+// Vector part, one workgroup per batch, sequential over its blocks: per band
+// the exact raw block sum (fixed-order sum over splits), block mean m_b,
+// e = m_b - shift, d = m_b - window mean before the block, window sums after
+// the block; per block the pairwise-update weight N n_b / (N + n_b) (0 when
+// the window was empty: the block's scatter replaces the window's).
+__global__ void __launch_bounds__(NT) k_merge_vec(LaunchSet ls) {
+  int local;
+  const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
-  int I, J;
-  sup_ij(sup, I, J);
-  const bool diag = (I == J);
-  __shared__ double s1w[128];   // window raw sums: rows 0..63 = bands 64I.., 64..127 = bands 64J..
-  __shared__ double ev[128];    // block mean minus shift
-  __shared__ double dv[128];    // block mean minus window mean (before the block)
-  const int tid = threadIdx.x;
-  const int64_t bp2 = (int64_t)d.Bp * d.Bp;
-
-  double m2[16];
-  int gi[16], gj[16];
-  bool val[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int idx = tid + NT * q;
-    gi[q] = 64 * I + idx / 64;
-    gj[q] = 64 * J + idx % 64;
-    val[q] = gi[q] < d.B && gj[q] < d.B && gi[q] >= gj[q];
-    m2[q] = val[q] ? d.m2_in[(int64_t)gi[q] * d.Bp + gj[q]] : 0.0;
+  for (int k = threadIdx.x; k < d.Bp; k += NT) {
+    double N = (double)d.n_in;
+    double s1 = (k < d.B) ? d.s1_in[k] : 0.0;
+    for (int b = 0; b < d.nblk; ++b) {
+      const double nb = (double)blk_lines_of(d, b) * d.S;
+      const int ksb = ks_of(d, b);
+      if ((d.reset_bits >> b) & 1ull) { N = 0.0; s1 = 0.0; }
+      double sb = 0.0;
+      if (k < d.B)
+        for (int s = 0; s < ksb; ++s) sb += d.psum[((int64_t)b * d.ks + s) * d.Bp + k];
+      const double mb = sb / nb;
+      const int64_t o = (int64_t)b * d.Bp + k;
+      d.ev[o] = (k < d.B) ? mb - d.shift[o] : 0.0;
+      d.dv[o] = (k < d.B && N > 0.0) ? mb - s1 / N : 0.0;
+      if (k == 0) d.coef[b] = N > 0.0 ? N * nb / (N + nb) : 0.0;
+      s1 += sb;
+      N += nb;
+      d.mu_snap[o] = (k < d.B) ? s1 / N : 0.0;
+      if (k == 0) d.n_snap[b] = N;
+    }
+    d.s1_out[k] = (k < d.B) ? s1 : 0.0;
   }
-  const int myband = tid < 64 ? 64 * I + tid : 64 * J + (tid - 64);
-  if (tid < 128) s1w[tid] = (myband < d.B) ? d.s1_in[myband] : 0.0;
-  double N = (double)d.n_in;
-  __syncthreads();
+}
 
+// Matrix part, one workgroup per lower 16x16 tile, one element per thread:
+// C_b = fixed-order FP64 sum of the split partials, M2_b = C_b - n_b e e^T
+// (exact shift correction), then the pairwise update
+// M2 <- M2 + M2_b + w d d^T  (or M2 <- M2_b for an empty window), with the
+// window's scatter matrix snapshotted after every block.
+template <typename PT>
+__global__ void __launch_bounds__(NT) k_merge_mat(LaunchSet ls) {
+  int t;
+  const int bi = find_batch(ls, blockIdx.x, t);
+  const BatchDesc& d = ls.d[bi];
+  int ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int gi = 16 * ti + (threadIdx.x >> 4), gj = 16 * tj + (threadIdx.x & 15);
+  if (!(gi < d.B && gj < d.B && gi >= gj)) return;
+  const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
+  double m2 = d.m2_in[e];
   for (int b = 0; b < d.nblk; ++b) {
     const double nb = (double)blk_lines_of(d, b) * d.S;
     const int ksb = ks_of(d, b);
-    const bool reset = (d.reset_bits >> b) & 1ull;
-    if (reset) {
-      N = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) m2[q] = 0.0;
-    }
-    if (tid < 128) {
-      double sb = 0.0;
-      if (myband < d.B)
-        for (int s = 0; s < ksb; ++s) sb += d.psum[((int64_t)b * d.ks + s) * d.Bp + myband];
-      const double sw = reset ? 0.0 : s1w[tid];
-      const double mb = sb / nb;
-      ev[tid] = (myband < d.B) ? mb - d.shift[(int64_t)b * d.Bp + myband] : 0.0;
-      dv[tid] = (myband < d.B && N > 0.0) ? mb - sw / N : 0.0;
-      s1w[tid] = sw + sb;
-    }
-    __syncthreads();
-    const double coef = N > 0.0 ? N * nb / (N + nb) : 0.0;
-    const PT* pb = static_cast<const PT*>(d.part) + ((int64_t)b * d.ks * d.nsup + sup) * (SUP * SUP);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      if (!val[q]) continue;
-      const int idx = tid + NT * q;
-      double c = 0.0;
-      for (int s = 0; s < ksb; ++s) c += (double)pb[(int64_t)s * d.nsup * (SUP * SUP) + idx];
-      const int ri = idx / 64, cj = idx % 64 + (diag ? 0 : 64);
-      const double m2b = c - nb * ev[ri] * ev[cj];
-      m2[q] = (N > 0.0) ? m2[q] + m2b + coef * dv[ri] * dv[cj] : m2b;
-      d.m2_snap[b * bp2 + (int64_t)gi[q] * d.Bp + gj[q]] = m2[q];
-    }
-    N += nb;
-    if (diag && tid < 64 && myband < d.Bp)
-      d.mu_snap[(int64_t)b * d.Bp + myband] = (myband < d.B) ? s1w[tid] / N : 0.0;
-    if (sup == 0 && tid == 0) d.n_snap[b] = N;
-    __syncthreads();
+    if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
+    const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
+    double c = 0.0;
+    for (int s = 0; s < ksb; ++s) c += (double)pb[s * bp2];
+    const int64_t o = (int64_t)b * d.Bp;
+    const double m2b = c - nb * d.ev[o + gi] * d.ev[o + gj];
+    const double w = d.coef[b];
+    m2 = (w > 0.0) ? m2 + m2b + w * d.dv[o + gi] * d.dv[o + gj] : m2b;
+    d.m2_snap[b * bp2 + e] = m2;
   }
-#pragma unroll
-  for (int q = 0; q < 16; ++q)
-    if (val[q]) d.m2_out[(int64_t)gi[q] * d.Bp + gj[q]] = m2[q];
-  if (diag && tid < 64 && myband < d.Bp) d.s1_out[myband] = s1w[tid];
+  d.m2_out[e] = m2;
 }
 
 }  // namespace rxk
 
-// Host entry used by the runtime: one LaunchSet per kernel phase.  Workgroup
-// prefixes differ per kernel, so the runtime passes three copies.
-extern "C" hipError_t rxk_launch_stats(int in_type, int prec, const rxk::LaunchSet* ls_shift,
-                                       const rxk::LaunchSet* ls_syrk, const rxk::LaunchSet* ls_merge,
-                                       int wg_shift, int wg_syrk, int wg_merge, hipStream_t st) {
+// Host entry used by the runtime: phase 0 centring shift, 1 covariance
+// product, 2 merge (vector then matrix part).  wg: workgroups of the phase
+// (for phase 2: wg = vector workgroups, wg2 = matrix workgroups).
+extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const rxk::LaunchSet* ls, int wg,
+                                       const rxk::LaunchSet* ls2, int wg2, hipStream_t st) {
   using namespace rxk;
-#define RXK_CASE(INV, PV)                                                                 \
-  if (in_type == INV && prec == PV) {                                                     \
-    if (wg_shift > 0) hipLaunchKernelGGL((k_shift<INV, PV>), dim3(wg_shift), dim3(NT), 0, st, *ls_shift); \
-    if (wg_syrk > 0) hipLaunchKernelGGL((k_syrk<INV, PV>), dim3(wg_syrk), dim3(NT), 0, st, *ls_syrk);     \
-    if (wg_merge > 0) {                                                                   \
-      if (PV == P_F64) hipLaunchKernelGGL((k_merge<double>), dim3(wg_merge), dim3(NT), 0, st, *ls_merge); \
-      else hipLaunchKernelGGL((k_merge<float>), dim3(wg_merge), dim3(NT), 0, st, *ls_merge);              \
-    }                                                                                     \
-    return hipGetLastError();                                                             \
+  if (phase == 2) {
+    if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(NT), 0, st, *ls);
+    if (wg2 > 0) {
+      if (prec == P_F64) hipLaunchKernelGGL((k_merge_mat<double>), dim3(wg2), dim3(NT), 0, st, *ls2);
+      else hipLaunchKernelGGL((k_merge_mat<float>), dim3(wg2), dim3(NT), 0, st, *ls2);
+    }
+    return hipGetLastError();
+  }
+  if (wg <= 0) return hipSuccess;
+#define RXK_CASE(INV, PV)                                                                      \
+  if (in_type == INV && prec == PV) {                                                          \
+    if (phase == 0) hipLaunchKernelGGL((k_shift<INV, PV>), dim3(wg), dim3(NT), 0, st, *ls);    \
+    else hipLaunchKernelGGL((k_syrk<INV, PV>), dim3(wg), dim3(NT), 0, st, *ls);                \
+    return hipGetLastError();                                                                  \
   }
   RXK_CASE(IN_U16, P_F64) RXK_CASE(IN_U16, P_F32) RXK_CASE(IN_U16, P_BF16) RXK_CASE(IN_U16, P_F16)
   RXK_CASE(IN_F32, P_F64) RXK_CASE(IN_F32, P_F32) RXK_CASE(IN_F32, P_BF16) RXK_CASE(IN_F32, P_F16)

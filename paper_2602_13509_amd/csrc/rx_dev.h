@@ -186,17 +186,19 @@ struct BatchDesc {
   int64_t n_in;           // window pixel count before the batch
   // statistics scratch
   double* shift;          // [nblk][Bp] per-block centring shift (FP32-representable on mixed paths)
-  void* part;             // [nblk][ks][nsup][64*64] centred scatter partials (float, or double on FP64)
+  void* part;             // [nblk][ks][Bp*Bp] centred scatter partials, lower part (float, or double on FP64)
   double* psum;           // [nblk][ks][Bp] raw per-band sums of each split (written by diagonal super-tiles)
   double* mu_snap;        // [nblk][Bp] window mean after block b
   double* m2_snap;        // [nblk][Bp*Bp] window scatter matrix after block b (lower triangle)
   double* n_snap;         // [nblk] window pixel count after block b
+  double* ev;             // [nblk][Bp] block mean minus shift
+  double* dv;             // [nblk][Bp] block mean minus the window mean before the block
+  double* coef;           // [nblk] pairwise-update weight N n_b / (N + n_b), 0 for an empty window
   // resident window state (ping-pong between batches)
   const double* s1_in; double* s1_out;   // [Bp] raw band sums of the window
   const double* m2_in; double* m2_out;   // [Bp*Bp] scatter matrix of the window (lower)
   // factorisation
   double* w64;            // [nblk][Bp*Bp] W = L^{-1} S (row-major lower, FP64)
-  double* wt64;           // [nblk][Bp*Bp] scratch: transpose of the partial inverse
   void* wlp;              // [nblk][Bp*Bp] whitening operand in whiten precision, scaled
   float* iscale;          // [nblk][Bp] input scale 2^-e_k applied to centred values
   float* oscale;          // [nblk][Bp] output row scale 2^f_i

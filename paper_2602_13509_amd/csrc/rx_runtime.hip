@@ -25,9 +25,8 @@
 
 using namespace rxk;
 
-extern "C" hipError_t rxk_launch_stats(int in_type, int prec, const LaunchSet* ls_shift, const LaunchSet* ls_syrk,
-                                       const LaunchSet* ls_merge, int wg_shift, int wg_syrk, int wg_merge,
-                                       hipStream_t st);
+extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const LaunchSet* ls, int wg,
+                                       const LaunchSet* ls2, int wg2, hipStream_t st);
 extern "C" hipError_t rxk_launch_factor(int wprec, const LaunchSet* ls, int wg, int Bw, hipStream_t st);
 extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const LaunchSet* ls, int wg, int Bw,
                                         hipStream_t st);
@@ -102,7 +101,7 @@ struct Block {
 };
 
 struct Sizes {
-  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status;
+  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status, ev, coef;
 };
 
 static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
@@ -112,7 +111,8 @@ static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
   const size_t psz = sp == RX_FP64 ? 8 : 4;
   Sizes z;
   z.shift = (size_t)nblk * Bp * 8;
-  z.part = (size_t)nblk * ks * nsup * SUP * SUP * psz;
+  z.part = (size_t)nblk * ks * Bp * Bp * psz;
+  (void)nsup;
   z.psum = (size_t)nblk * ks * Bp * 8;
   z.mu = (size_t)nblk * Bp * 8;
   z.m2 = (size_t)nblk * Bp * Bp * 8;
@@ -121,6 +121,8 @@ static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
   z.wlp = (size_t)nblk * Bp * Bw * 4;
   z.scl = (size_t)nblk * Bp * 4;
   z.status = (size_t)nblk * 4;
+  z.ev = (size_t)nblk * Bp * 8;
+  z.coef = (size_t)nblk * 8;
   return z;
 }
 
@@ -142,7 +144,7 @@ struct rx_stream {
   int64_t N = 0;
   int64_t lines_seen = 0;
   // batch scratch
-  DevBuf shift, part, psum, mu, m2s, nsnap, w64, wt64, wlp, isc, osc, status, nsing;
+  DevBuf shift, part, psum, mu, m2s, nsnap, w64, wlp, isc, osc, status, nsing, evb, dvb, coefb;
   unsigned last_nsing = 0;
   // pending scores
   DevBuf pend[2];
@@ -233,7 +235,8 @@ static size_t stream_bytes(const rx_config* c, int max_block_lines) {
   const int Bp = pad16(c->bands);
   const Sizes z = scratch_sizes(c->bands, c->samples, c->syrk_prec, 1, std::max(1, max_block_lines));
   const size_t state = 2 * ((size_t)Bp * 8 + (size_t)Bp * Bp * 8);
-  const size_t scr = z.shift + z.part + z.psum + z.mu + z.m2 + z.nsnap + 2 * z.w64 + z.wlp + 2 * z.scl + z.status;
+  const size_t scr = z.shift + z.part + z.psum + z.mu + z.m2 + z.nsnap + z.w64 + z.wlp + 2 * z.scl + z.status +
+                     2 * z.ev + z.coef;
   const size_t esz = c->whiten_prec == RX_FP64 ? 8 : 4;
   const size_t pend = 2 * (size_t)std::max(1, max_block_lines) * c->samples * esz;
   return state + scr + pend;
@@ -250,7 +253,7 @@ extern "C" rx_status rx_stream_footprint(const rx_config* cfg, int32_t max_block
 // ---------------------------------------------------------------------------- init / destroy
 static void free_stream(rx_stream* s) {
   DevBuf* bufs[] = {&s->s1[0], &s->s1[1], &s->m2[0], &s->m2[1], &s->shift, &s->part, &s->psum, &s->mu,
-                    &s->m2s, &s->nsnap, &s->w64, &s->wt64, &s->wlp, &s->isc, &s->osc, &s->status,
+                    &s->m2s, &s->nsnap, &s->w64, &s->wlp, &s->isc, &s->osc, &s->status, &s->evb, &s->dvb, &s->coefb,
                     &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
   for (DevBuf* b : bufs) dev_free(*b);
   if (s->host_pin) (void)hipHostFree(s->host_pin);
@@ -276,11 +279,13 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   if ((r = dev_ensure(s->m2s, z.m2, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->nsnap, z.nsnap, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->w64, z.w64, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->wt64, z.w64, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->wlp, z.wlp, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->isc, z.scl, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->osc, z.scl, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->status, z.status, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->evb, z.ev, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->dvb, z.ev, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->coefb, z.coef, s->st)) != RX_OK) return r;
   return RX_OK;
 }
 
@@ -402,7 +407,7 @@ struct Job {
   rx_stream* s;
   BatchDesc d;
   int in_type, sp, wp, Bw;
-  int wg_shift, wg_syrk, wg_merge, wg_factor, wg_whiten;
+  int wg_shift, wg_syrk, wg_merge, wg_mmat, wg_factor, wg_whiten;
 };
 
 // Cut n_lines starting at stream line `pos` into blocks.
@@ -473,12 +478,14 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.mu_snap = static_cast<double*>(s->mu.p);
   d.m2_snap = static_cast<double*>(s->m2s.p);
   d.n_snap = static_cast<double*>(s->nsnap.p);
+  d.ev = static_cast<double*>(s->evb.p);
+  d.dv = static_cast<double*>(s->dvb.p);
+  d.coef = static_cast<double*>(s->coefb.p);
   d.s1_in = static_cast<const double*>(s->s1[s->cur].p);
   d.s1_out = static_cast<double*>(s->s1[1 - s->cur].p);
   d.m2_in = static_cast<const double*>(s->m2[s->cur].p);
   d.m2_out = static_cast<double*>(s->m2[1 - s->cur].p);
   d.w64 = static_cast<double*>(s->w64.p);
-  d.wt64 = static_cast<double*>(s->wt64.p);
   d.wlp = s->wlp.p;
   d.iscale = static_cast<float*>(s->isc.p);
   d.oscale = static_cast<float*>(s->osc.p);
@@ -493,7 +500,8 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.Bw = s->Bw;
   j.wg_shift = nblk * (s->Bp / 4);
   j.wg_syrk = d.nsup * ((nblk - 1) * d.ks + d.ks_last);
-  j.wg_merge = d.nsup;
+  j.wg_merge = 1;
+  j.wg_mmat = (s->Bp / 16) * (s->Bp / 16 + 1) / 2;
   j.wg_factor = nblk;
   j.wg_whiten = (int)(lines * s->cpl);
 
@@ -570,20 +578,21 @@ static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* 
   };
   rx_status r = run_groups([](const Job& j) { return j.in_type * 16 + j.sp; },
                            [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
-                             LaunchSet a, b, c;
+                             LaunchSet a, b, c, e;
                              const int n1 = fill(a, grp, g0, g1, &Job::wg_shift);
                              const int n2 = fill(b, grp, g0, g1, &Job::wg_syrk);
                              const int n3 = fill(c, grp, g0, g1, &Job::wg_merge);
+                             const int n4 = fill(e, grp, g0, g1, &Job::wg_mmat);
                              const int it = jobs[grp[g0]].in_type, sp = jobs[grp[g0]].sp;
                              rx_status q;
                              if ((q = prof_mark(prof, 0, true, st)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, &a, &b, &c, n1, 0, 0, st));
+                             HIPC(rxk_launch_stats(it, sp, 0, &a, n1, nullptr, 0, st));
                              if ((q = prof_mark(prof, 0, false, st)) != RX_OK) return q;
                              if ((q = prof_mark(prof, 1, true, st)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, &a, &b, &c, 0, n2, 0, st));
+                             HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, st));
                              if ((q = prof_mark(prof, 1, false, st)) != RX_OK) return q;
                              if ((q = prof_mark(prof, 2, true, st)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, &a, &b, &c, 0, 0, n3, st));
+                             HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, st));
                              return prof_mark(prof, 2, false, st);
                            });
   if (r != RX_OK) return r;
