@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
         tl[s][r] = v;
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
+    if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // at most four tiles of loads in flight
   }
   for (int k = 0; k < T; ++k) {
     int offA = offA0, offB = offB0;
@@ -140,13 +140,20 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
-    // 16x16 Cholesky of the diagonal tile in wave 0: lane = (row i, column group cg of 4)
+    // 16x16 Cholesky of the diagonal tile and Y = L_kk^{-1} together, in wave 0:
+    // lane = (row i, column group cg of 4) holds S[i][4cg..4cg+3] and the
+    // eliminated identity E[i][4cg..4cg+3].  Column j: pivot d = sqrt(S[j][j]),
+    // L[i][j] = S[i][j] / d, Y[j][.] = E[j][.] / d, then S[i][k] -= L[i][j] L[k][j]
+    // (j < k <= i) and E[i][.] -= L[i][j] Y[j][.] (i > j).
     if (wv == 0) {
       int i = lane & 15, cg = lane >> 4;
       asm volatile("" : "+v"(i), "+v"(cg));    // shuffle addresses are formed per step, not hoisted
-      double v[4];
+      double v[4], y[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = T22[i][4 * cg + e];
+      for (int e = 0; e < 4; ++e) {
+        v[e] = T22[i][4 * cg + e];
+        y[e] = (i == 4 * cg + e) ? 1.0 : 0.0;
+      }
       bool bad = false;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
@@ -155,33 +162,26 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
         bad |= !(piv > 0.0);
         const double rd = 1.0 / sqrt(piv);
         const double lij = __shfl(v[je], i + 16 * jg, 64) * rd;
-        double lkj[4];
+        double lkj[4], yj[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
+        for (int e = 0; e < 4; ++e) {
+          lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
+          yj[e] = __shfl(y[e], j + 16 * cg, 64) * rd;
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int kk = 4 * cg + e;
           if (kk > j && i >= kk) v[e] -= lij * lkj[e];
+          y[e] = (i == j) ? yj[e] : ((i > j) ? y[e] - lij * yj[e] : y[e]);
         }
-        if (cg == jg) v[je] = (i > j) ? lij : (i == j ? piv * rd : 0.0);
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) T22[i][4 * cg + e] = v[e];
+      for (int e = 0; e < 4; ++e) ybuf[i * 17 + 4 * cg + e] = y[e];
       if (lane == 0 && bad) flag = 1;
     }
     __syncthreads();
     if (flag) break;
-    if (tid < 16) {                 // Y = L_kk^{-1}, one column per lane, built in place in LDS
-      const int q = tid;
-#pragma unroll 1
-      for (int i = 0; i < 16; ++i) {
-        double s2 = (i == q) ? 1.0 : 0.0;
-        for (int m = 0; m < i; ++m) s2 -= T22[i][m] * ybuf[m * 17 + q];
-        ybuf[i * 17 + q] = (i >= q) ? s2 / T22[i][i] : 0.0;
-      }
-    }
-    __syncthreads();
     // pivot column L_ik = R_ik Y^T, pivot row W_kj = Y E_kj, W_kk = Y
 #pragma unroll
     for (int s = 0; s < FTPW; ++s) {
@@ -244,60 +244,50 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
     if (tid == 0) { d.status[b] = 1; atomicAdd(d.nsing, 1u); }
     return;
   }
-  // ---- W = L^{-1} S (FP64, row-major), zero above the diagonal and in the padding
+  // ---- W = L^{-1} S (FP64, row-major) and the whitening operand in the whitening
+  // precision, from the tiles.  Tiles above the diagonal are never written:
+  // those parts of both buffers are zeroed once when they are allocated.
+  constexpr bool LP = (WP == P_BF16 || WP == P_F16 || WP == P_FP8);
+  constexpr int top = (WP == P_FP8) ? 7 : 14;     // scaled row maximum lands in [2^top, 2^(top+1))
+  __shared__ int ek[MAXBP];
+  __shared__ int fi[MAXBP];
+  for (int k = tid; k < Bp; k += FNT) ek[k] = (LP && k < B) ? ilogb(1.0 / sc[k]) : 0;   // 2^e <= sigma_k < 2^(e+1)
 #pragma unroll
   for (int s = 0; s < FTPW; ++s) {
     if (ti[s] >= 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * ti[s] + lg + 4 * r, col = 16 * tj[s] + lr;
-        W[(int64_t)row * Bp + col] = (row < B && col < B && col <= row) ? tl[s][r] * sc[col] : 0.0;
+        const double v = (row < B && col < B && col <= row) ? tl[s][r] * sc[col] : 0.0;
+        tl[s][r] = v;
+        W[(int64_t)row * Bp + col] = v;
       }
     }
   }
-  for (int64_t idx = tid; idx < bp2; idx += FNT) {
-    const int i = (int)(idx / Bp), j = (int)(idx % Bp);
-    if ((j >> 4) > (i >> 4)) W[idx] = 0.0;
-  }
-  __syncthreads();
-
-
-  // ---- whitening operand in the whitening precision
-  if constexpr (WP == P_F32) {
-    float* wl = static_cast<float*>(d.wlp) + (int64_t)b * Bp * Bw;
-    for (int64_t idx = tid; idx < (int64_t)Bp * Bw; idx += FNT) {
-      const int i = (int)(idx / Bw), j = (int)(idx % Bw);
-      wl[idx] = (j < Bp) ? (float)W[(int64_t)i * Bp + j] : 0.0f;
-    }
-    for (int k = tid; k < Bp; k += FNT) {
-      d.iscale[(int64_t)b * Bp + k] = 1.0f;
-      d.oscale[(int64_t)b * Bp + k] = 1.0f;
-    }
-  } else if constexpr (WP != P_F64) {
+  if constexpr (WP != P_F64) {
     using S = typename MM<WP>::storage;
     S* wl = static_cast<S*>(d.wlp) + (int64_t)b * Bp * Bw;
-    constexpr int top = (WP == P_FP8) ? 7 : 14;     // row max lands in [2^top, 2^(top+1))
-    __shared__ int ek[MAXBP];
-    __shared__ int fi[MAXBP];
+    __syncthreads();
+    if constexpr (LP) {           // row maxima of |W_ij 2^e_j|: one wave per row, lanes over columns
+      for (int i = wv; i < Bp; i += FNW) {
+        double m = 0.0;
+        for (int j = lane; j <= i && j < B; j += 64) m = fmax(m, fabs(ldexp(W[(int64_t)i * Bp + j], ek[j])));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) fi[i] = (m > 0.0) ? ilogb(m) - top : 0;
+      }
+    } else {
+      for (int k = tid; k < Bp; k += FNT) fi[k] = 0;
+    }
+    __syncthreads();
     for (int k = tid; k < Bp; k += FNT) {
-      const int e = (k < B) ? ilogb(1.0 / sc[k]) : 0;   // 2^e <= sigma_k < 2^(e+1)
-      ek[k] = e;
-      d.iscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, -e);
+      d.iscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, -ek[k]);
+      d.oscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, fi[k]);
     }
-    __syncthreads();
-    for (int i = tid; i < Bp; i += FNT) {
-      double m = 0.0;
-      for (int j = 0; j <= i && j < B; ++j) m = fmax(m, fabs(ldexp(W[(int64_t)i * Bp + j], ek[j])));
-      const int f = (m > 0.0) ? ilogb(m) - top : 0;
-      fi[i] = f;
-      d.oscale[(int64_t)b * Bp + i] = (float)ldexp(1.0, f);
-    }
-    __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)Bp * Bw; idx += FNT) {
-      const int i = (int)(idx / Bw), j = (int)(idx % Bw);
-      float v = 0.0f;
-      if (j < Bp) v = (float)ldexp(W[(int64_t)i * Bp + j], ek[j] - fi[i]);
-      wl[idx] = to_storage<WP>(v);
+    // one wave per row, lanes over the columns of the row's lower tiles
+    for (int i = wv; i < Bp; i += FNW) {
+      const int jend = 16 * (i / 16 + 1);
+      for (int j = lane; j < jend; j += 64)
+        wl[(int64_t)i * Bw + j] = to_storage<WP>((float)ldexp(W[(int64_t)i * Bp + j], ek[j] - fi[i]));
     }
   }
   if (tid == 0) d.status[b] = 0;

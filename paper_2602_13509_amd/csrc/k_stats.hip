@@ -13,6 +13,8 @@
 //               partials, exact shift correction M2_b = C - n e e^T
 //               (e = m_b - c), then the pairwise (Chan-Golub-LeVeque) update
 //               of the window (N, S1, M2), snapshotting it after every block.
+#include <type_traits>
+
 #include "rx_dev.h"
 
 namespace rxk {
@@ -170,57 +172,431 @@ __global__ void __launch_bounds__(NT) k_syrk(LaunchSet ls) {
   }
 }
 
-// ---------------------------------------------------------------------------- merge
-// Vector part, one workgroup per batch, sequential over its blocks: per band
-// the exact raw block sum (fixed-order sum over splits), block mean m_b,
-// e = m_b - shift, d = m_b - window mean before the block, window sums after
-// the block; per block the pairwise-update weight N n_b / (N + n_b) (0 when
-// the window was empty: the block's scatter replaces the window's).
-__global__ void __launch_bounds__(NT) k_merge_vec(LaunchSet ls) {
+// ---------------------------------------------------------------------------- covariance product, 8-value formats
+// One 1024-thread workgroup = (block b, split s) owns the WHOLE lower triangle
+// for its pixel range, so every input element is read from memory once and
+// the split partial is one Bp x Bp matrix.  Chunks of KC pixels (one line
+// segment) are centred, rounded to the operand format and staged in LDS as
+// [band][k] (double-buffered, the next chunk's loads in flight while the
+// current one is multiplied).  Wave w owns a rectangle of at most 4 x 4
+// 16-band tiles (rect table from the host; at most 15 rectangles for
+// B <= 320): per 32-pixel step it reads its row fragments once and each
+// column fragment once from LDS.  Raw band sums ride along in the staging.
+constexpr int S2NT = 1024;
+constexpr int S2LDK = KC + 8;              // LDS row pitch (elements)
+constexpr int S2IT = (16 * MAXT * 8 + S2NT - 1) / S2NT;   // staging items per thread
+
+template <int IN, int P>
+__global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
+  using M = MM<P>;
+  using S = typename M::storage;
+  using T = typename InT<IN>::T;
+  static_assert(M::KV == 8, "8-value operand formats only");
+  __shared__ __attribute__((aligned(16))) S tile[2][16 * MAXT * S2LDK];
+
   int local;
   const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
-  for (int k = threadIdx.x; k < d.Bp; k += NT) {
-    double N = (double)d.n_in;
-    double s1 = (k < d.B) ? d.s1_in[k] : 0.0;
-    for (int b = 0; b < d.nblk; ++b) {
-      const double nb = (double)blk_lines_of(d, b) * d.S;
-      const int ksb = ks_of(d, b);
-      if ((d.reset_bits >> b) & 1ull) { N = 0.0; s1 = 0.0; }
-      double sb = 0.0;
-      if (k < d.B)
-        for (int s = 0; s < ksb; ++s) sb += d.psum[((int64_t)b * d.ks + s) * d.Bp + k];
-      const double mb = sb / nb;
-      const int64_t o = (int64_t)b * d.Bp + k;
-      d.ev[o] = (k < d.B) ? mb - d.shift[o] : 0.0;
-      d.dv[o] = (k < d.B && N > 0.0) ? mb - s1 / N : 0.0;
-      if (k == 0) d.coef[b] = N > 0.0 ? N * nb / (N + nb) : 0.0;
-      s1 += sb;
-      N += nb;
-      d.mu_snap[o] = (k < d.B) ? s1 / N : 0.0;
-      if (k == 0) d.n_snap[b] = N;
+  int b = local / d.ks, split = local % d.ks;
+  if (b >= d.nblk - 1) { b = d.nblk - 1; split = local - (d.nblk - 1) * d.ks; }
+  const int ksb = ks_of(d, b);
+  const int lines_b = blk_lines_of(d, b);
+  const int64_t nch = (int64_t)lines_b * d.cpl;
+  const int64_t c0 = nch * split / ksb, c1 = nch * (split + 1) / ksb;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const T* xb = static_cast<const T*>(d.x) + (int64_t)b * d.blk_lines * d.B * d.S;
+
+  // staging items: item = row * 8 + segment of 8 samples, fixed per thread.
+  // Raw sums are exact: uint32 for 16-bit input (at most 80 chunks x 8 values
+  // x 65535 per thread), FP64 otherwise.
+  using RS = typename std::conditional<IN == IN_U16, uint32_t, double>::type;
+  float shf[S2IT];
+  RS rawsum[S2IT];
+#pragma unroll
+  for (int q = 0; q < S2IT; ++q) {
+    const int r = (tid + S2NT * q) >> 3;
+    shf[q] = (r < d.B) ? (float)d.shift[(int64_t)b * d.Bp + r] : 0.0f;
+    rawsum[q] = RS(0);
+  }
+  auto row_of = [&](int q) { const int it = tid + S2NT * q; return (it < d.Bp * 8) ? (it >> 3) : -1; };
+  const int k0 = 8 * (tid & 7);
+  constexpr int RW = 8 * (int)sizeof(T) / 16;     // 16-byte words per 8 input values
+  uint4 raw[S2IT][RW];                              // next chunk, kept packed until it is staged
+  auto load = [&](int64_t ch) {
+    const int line = (int)(ch / d.cpl);
+    const int s0 = (int)(ch % d.cpl) * KC;
+    const int nvalid = min(KC, d.S - s0);
+#pragma unroll
+    for (int q = 0; q < S2IT; ++q) {
+      const int r = row_of(q);
+      if (r >= 0 && r < d.B) {
+        const T* row = xb + ((int64_t)line * d.B + r) * d.S + s0;
+        if (d.vec_ok && k0 + 8 <= nvalid) {
+#pragma unroll
+          for (int w = 0; w < RW; ++w) raw[q][w] = reinterpret_cast<const uint4*>(row + k0)[w];
+        } else {
+          T t[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) t[j] = (k0 + j < nvalid) ? row[k0 + j] : T(0);
+          pack8(t, raw[q]);
+        }
+      }
     }
-    d.s1_out[k] = (k < d.B) ? s1 : 0.0;
+    return nvalid;
+  };
+  auto store = [&](int buf, int nvalid) {
+#pragma unroll
+    for (int q = 0; q < S2IT; ++q) {
+      const int r = row_of(q);
+      if (r < 0) continue;
+      T vv[8];
+      unpack8(raw[q], vv);
+      S o[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const bool ok = (r < d.B) && (k0 + j < nvalid);
+        float dv;
+        if constexpr (IN == IN_F64) dv = (float)(vv[j] - (double)d.shift[(int64_t)b * d.Bp + r]);
+        else dv = (float)vv[j] - shf[q];
+        o[j] = to_storage<P>(ok ? dv : 0.0f);
+        if (ok) rawsum[q] += (RS)vv[j];
+      }
+      uint4 ow;
+      ow.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16); ow.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+      ow.z = (uint32_t)o[4] | ((uint32_t)o[5] << 16); ow.w = (uint32_t)o[6] | ((uint32_t)o[7] << 16);
+      *reinterpret_cast<uint4*>(&tile[buf][r * S2LDK + k0]) = ow;
+    }
+  };
+
+  // this wave's rectangle
+  const int rr0 = (wv < d.nrect) ? d.rect[wv][0] : 0, rc0 = (wv < d.nrect) ? d.rect[wv][1] : 0;
+  const int rnr = (wv < d.nrect) ? d.rect[wv][2] : 0, rnc = (wv < d.nrect) ? d.rect[wv][3] : 0;
+  typename M::acc acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename M::acc{};
+  const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+  int buf = 0;
+  if (c0 < c1) {
+    const int nv = load(c0);
+    store(0, nv);
+  }
+  __syncthreads();
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    int nvn = 0;
+    const bool more = ch + 1 < c1;
+    if (more) nvn = load(ch + 1);             // next chunk's loads in flight during the products
+    const S* tb = tile[buf];
+#pragma unroll
+    for (int st = 0; st < KC / 32; ++st) {
+      const int kk = 32 * st + lk;
+      typename M::frag a[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (i < rnr) a[i] = load_frag<P>(&tb[(16 * (rr0 + i) + lr) * S2LDK + kk]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j < rnc) {
+          const typename M::frag bf = load_frag<P>(&tb[(16 * (rc0 + j) + lr) * S2LDK + kk]);
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (i < rnr && rr0 + i >= rc0 + j) acc[i][j] = M::mma(a[i], bf, acc[i][j]);
+        }
+      }
+    }
+    if (more) store(buf ^ 1, nvn);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // partial scatter of this split: lower tiles of the rectangle into the Bp x Bp matrix
+  const int64_t slot = (int64_t)b * d.ks + split;
+  using C = typename M::accs;
+  C* out = static_cast<C*>(d.part) + slot * d.Bp * d.Bp;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (i < rnr && j < rnc && rr0 + i >= rc0 + j) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int gi = 16 * (rr0 + i) + M::out_row(lane >> 4, e), gj = 16 * (rc0 + j) + lr;
+          out[(int64_t)gi * d.Bp + gj] = acc[i][j][e];
+        }
+      }
+  // raw band sums: the 8 segments of a row are 8 adjacent lanes
+#pragma unroll
+  for (int q = 0; q < S2IT; ++q) {
+    double t = (double)rawsum[q];
+    t += __shfl_xor(t, 1, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 4, 64);
+    const int r = row_of(q);
+    if ((tid & 7) == 0 && r >= 0) d.psum[slot * d.Bp + r] = t;
   }
 }
 
-// Matrix part, one workgroup per lower 16x16 tile, one element per thread:
-// C_b = fixed-order FP64 sum of the split partials, M2_b = C_b - n_b e e^T
-// (exact shift correction), then the pairwise update
-// M2 <- M2 + M2_b + w d d^T  (or M2 <- M2_b for an empty window), with the
-// window's scatter matrix snapshotted after every block.
-template <typename PT>
-__global__ void __launch_bounds__(NT) k_merge_mat(LaunchSet ls) {
-  int t;
-  const int bi = find_batch(ls, blockIdx.x, t);
+// ---------------------------------------------------------------------------- covariance product, 16-bit input, direct-to-LDS staging
+// As k_syrk2, for 16-bit input with 16-byte aligned rows: the raw chunks are
+// loaded straight into a three-deep LDS ring (global_load_lds_dwordx4, no
+// registers), two chunks ahead of the one being multiplied.  Row r's eight
+// 16-byte segments are stored XOR-swizzled (slot = segment ^ (r & 7)) so
+// the 16-row fragment reads hit distinct banks; each thread converts its own
+// slots in place (centred in FP32, rounded to the operand format) and keeps
+// the exact raw band sums.  Every wave issues the same loads for every chunk,
+// so waiting for a chunk is a fixed count of outstanding loads.
+constexpr int S3ROWS = 16 * MAXT;          // rows per ring buffer
+
+// Workgroup barrier that orders LDS accesses only.  A plain __syncthreads()
+// also waits for every outstanding global access of the wave, which would
+// drain the direct-to-LDS loads queued for later chunks; those are waited for
+// explicitly, chunk by chunk, before the barrier that publishes them.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int P>
+__global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
+  using M = MM<P>;
+  using S = typename M::storage;
+  static_assert(M::KV == 8 && sizeof(S) == 2, "16-bit operand formats only");
+  // three distinct LDS objects, used in a statically known rotation, so the
+  // compiler tracks the in-flight direct loads of each one separately
+  __shared__ __attribute__((aligned(16))) uint16_t ring0[S3ROWS * KC];
+  __shared__ __attribute__((aligned(16))) uint16_t ring1[S3ROWS * KC];
+  __shared__ __attribute__((aligned(16))) uint16_t ring2[S3ROWS * KC];
+  __shared__ float shl[S3ROWS];
+
+  int local;
+  const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
+  int b = local / d.ks, split = local % d.ks;
+  if (b >= d.nblk - 1) { b = d.nblk - 1; split = local - (d.nblk - 1) * d.ks; }
+  const int ksb = ks_of(d, b);
+  const int lines_b = blk_lines_of(d, b);
+  // chunk indices of one block fit in 32 bits (a block is a few thousand lines)
+  const int nch = lines_b * d.cpl;
+  const int c0 = (int)((int64_t)nch * split / ksb), c1 = (int)((int64_t)nch * (split + 1) / ksb);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint16_t* xb = static_cast<const uint16_t*>(d.x) + (int64_t)b * d.blk_lines * d.B * d.S;
+  const int lrow = lane >> 3, lslot = lane & 7;
+
+  auto issue = [&](int ch, uint16_t* buf) {
+    const unsigned line = (unsigned)ch / (unsigned)d.cpl;
+    const int s0 = (int)((unsigned)ch - line * (unsigned)d.cpl) * KC;
+    const int nvalid = min(KC, d.S - s0);
+#pragma unroll
+    for (int q = 0; q < S2IT; ++q) {
+      const int r0 = 128 * q + 8 * wv;           // wave-uniform
+      if (r0 < d.Bp) {
+        const int r = r0 + lrow;
+        const int seg = lslot ^ (r & 7);
+        const bool ok = (r < d.B) && (8 * seg < nvalid);
+        // lanes past the row end or the band count load a harmless in-bounds
+        // word; the conversion writes zeros over their slot
+        const uint16_t* src = ok ? xb + ((int64_t)line * d.B + r) * d.S + s0 + 8 * seg : xb;
+        __builtin_amdgcn_global_load_lds((const void*)src,
+                                         (__attribute__((address_space(3))) void*)(buf + r0 * KC), 16, 0, 0);
+      }
+    }
+  };
+  int nld = 0;                                   // direct loads per chunk of this wave
+#pragma unroll
+  for (int q = 0; q < S2IT; ++q) nld += (128 * q + 8 * wv < d.Bp) ? 1 : 0;
+
+  uint32_t rawsum[S2IT];
+#pragma unroll
+  for (int q = 0; q < S2IT; ++q) rawsum[q] = 0u;
+  for (int r = tid; r < d.Bp; r += S2NT) shl[r] = (r < d.B) ? (float)d.shift[(int64_t)b * d.Bp + r] : 0.0f;
+  // the direct path runs only when the sample count is a multiple of 8, so an
+  // 8-sample segment is either wholly inside the row or wholly past its end
+  auto convert = [&](int ch, uint16_t* buf) {
+    const int s0 = (int)((unsigned)ch % (unsigned)d.cpl) * KC;
+    const int nvalid = min(KC, d.S - s0);
+#pragma unroll
+    for (int q = 0; q < S2IT; ++q) {
+      const int it = tid + S2NT * q;
+      const int r = it >> 3, slot = it & 7;
+      if (r >= d.Bp) continue;
+      const int seg = slot ^ (r & 7);
+      const bool ok = (r < d.B) && (8 * seg < nvalid);
+      uint4* p = reinterpret_cast<uint4*>(buf + r * KC + 8 * slot);
+      uint16_t vv[8];
+      unpack8(p, vv);
+      const float sh = shl[r];
+      uint32_t o[4];
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        const S e0 = to_storage<P>(ok ? (float)vv[j] - sh : 0.0f);
+        const S e1 = to_storage<P>(ok ? (float)vv[j + 1] - sh : 0.0f);
+        o[j >> 1] = (uint32_t)e0 | ((uint32_t)e1 << 16);
+        rawsum[q] += ok ? (uint32_t)vv[j] + vv[j + 1] : 0u;
+      }
+      *p = uint4{o[0], o[1], o[2], o[3]};
+    }
+  };
+
+  // wave wv owns the 64x64 super-tile (I, J), I >= J, of the lower triangle
+  // (at most 15 of them for 320 bands); it multiplies all 16 tiles of it and
+  // keeps the lower ones.  Rows past the band count read ring rows that are
+  // either zero or never written out.
+  int I = 0, J = 0;
+  {
+    int t = wv;
+    while (t > I) { t -= I + 1; ++I; }
+    J = t;
+  }
+  const int nsup = (d.Bp + 63) >> 6;
+  const bool active = I < nsup;
+  typename M::acc acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename M::acc{};
+  const int lr = lane & 15, lkg = lane >> 4;
+
+  auto multiply = [&](const uint16_t* tb) {
+    if (!active) return;
+#pragma unroll
+    for (int st = 0; st < KC / 32; ++st) {
+      const int g = 4 * st + lkg;               // 8-value k-group within the chunk
+      const int off = lr * KC + 8 * (g ^ (lr & 7));
+      typename M::frag a[4], bq[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bq[j] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * J + 16 * j) * KC + off));
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) a[ii] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * I + 16 * ii) * KC + off));
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[ii][j] = M::mma(a[ii], bq[j], acc[ii][j]);
+    }
+  };
+  // one chunk: wait for its own loads (leave the next chunk's in flight),
+  // convert it in place, queue the chunk two ahead into the slot freed by the
+  // previous chunk, multiply
+  auto step = [&](int ch, uint16_t* cur, uint16_t* ahead) {
+    if (ch + 1 < c1) {
+      if (nld == 3) __builtin_amdgcn_s_waitcnt(0x0F70 | 3);
+      else if (nld == 2) __builtin_amdgcn_s_waitcnt(0x0F70 | 2);
+      else if (nld == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | 1);
+      else __builtin_amdgcn_s_waitcnt(0x0F70);
+    } else {
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    lds_barrier();
+    convert(ch, cur);
+    lds_barrier();
+    if (ch + 2 < c1) issue(ch + 2, ahead);
+    multiply(cur);
+  };
+
+  if (c0 < c1) issue(c0, ring0);
+  if (c0 + 1 < c1) issue(c0 + 1, ring1);
+  for (int ch = c0; ch < c1; ch += 3) {
+    step(ch, ring0, ring2);
+    if (ch + 1 < c1) step(ch + 1, ring1, ring0);
+    if (ch + 2 < c1) step(ch + 2, ring2, ring1);
+  }
+
+  const int64_t slot = (int64_t)b * d.ks + split;
+  using C = typename M::accs;
+  C* out = static_cast<C*>(d.part) + slot * d.Bp * d.Bp;
+  if (active) {
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int ti = 4 * I + ii, tj = 4 * J + j;
+        if (16 * ti < d.Bp && ti >= tj) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int gi = 16 * ti + M::out_row(lane >> 4, e), gj = 16 * tj + lr;
+            out[(int64_t)gi * d.Bp + gj] = acc[ii][j][e];
+          }
+        }
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < S2IT; ++q) {
+    double t = (double)rawsum[q];
+    t += __shfl_xor(t, 1, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 4, 64);
+    const int r = (tid + S2NT * q) >> 3;
+    if ((tid & 7) == 0 && r < d.Bp) d.psum[slot * d.Bp + r] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------- merge
+constexpr int MB = 64;      // threads per merge workgroup
+constexpr int MAXBLK = 64;  // blocks per batch (reset bits are a 64-bit mask)
+
+// Vector part: one wave per 64 bands.  First every block's exact raw band
+// sum (fixed-order sum over its splits) and shift are gathered (independent
+// loads, all in flight), then the sequential recurrence over blocks: block
+// mean m_b, e = m_b - shift, d = m_b - window mean before the block, window
+// sums after it, and per block the pairwise-update weight N n_b / (N + n_b)
+// (0 when the window was empty: the block's scatter replaces the window's).
+__global__ void __launch_bounds__(MB) k_merge_vec(LaunchSet ls) {
+  int local;
+  const int bi = find_batch(ls, blockIdx.x, local);
+  const BatchDesc& d = ls.d[bi];
+  __shared__ double sb[MAXBLK][MB];
+  __shared__ double shb[MAXBLK][MB];
+  const int k = MB * local + threadIdx.x;
+  const bool in = k < d.B;
+#pragma unroll 4
+  for (int b = 0; b < d.nblk; ++b) {
+    const int ksb = ks_of(d, b);
+    double t = 0.0;
+    if (in)
+      for (int s = 0; s < ksb; ++s) t += d.psum[((int64_t)b * d.ks + s) * d.Bp + k];
+    sb[b][threadIdx.x] = t;
+    shb[b][threadIdx.x] = (k < d.Bp) ? d.shift[(int64_t)b * d.Bp + k] : 0.0;
+  }
+  if (k >= d.Bp) return;
+  double N = (double)d.n_in;
+  double s1 = in ? d.s1_in[k] : 0.0;
+  for (int b = 0; b < d.nblk; ++b) {
+    const double nb = (double)blk_lines_of(d, b) * d.S;
+    if ((d.reset_bits >> b) & 1ull) { N = 0.0; s1 = 0.0; }
+    const double mb = sb[b][threadIdx.x] / nb;
+    const int64_t o = (int64_t)b * d.Bp + k;
+    d.ev[o] = in ? mb - shb[b][threadIdx.x] : 0.0;
+    d.dv[o] = (in && N > 0.0) ? mb - s1 / N : 0.0;
+    if (k == 0) d.coef[b] = N > 0.0 ? N * nb / (N + nb) : 0.0;
+    s1 += sb[b][threadIdx.x];
+    N += nb;
+    d.mu_snap[o] = in ? s1 / N : 0.0;
+    if (k == 0) d.n_snap[b] = N;
+  }
+  d.s1_out[k] = in ? s1 : 0.0;
+}
+
+// Matrix part: one wave per quarter of a lower 16x16 tile (4 rows x 16
+// columns), one element per lane: C_b = fixed-order FP64 sum of the split
+// partials, M2_b = C_b - n_b e e^T (exact shift correction), then the
+// pairwise update M2 <- M2 + M2_b + w d d^T (or M2 <- M2_b for an empty
+// window), the window's scatter matrix snapshotted after every block.
+template <typename PT>
+__global__ void __launch_bounds__(MB) k_merge_mat(LaunchSet ls) {
+  int q;
+  const int bi = find_batch(ls, blockIdx.x, q);
+  const BatchDesc& d = ls.d[bi];
+  const int t = q >> 2;
   int ti = 0;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int tj = t - ti * (ti + 1) / 2;
-  const int gi = 16 * ti + (threadIdx.x >> 4), gj = 16 * tj + (threadIdx.x & 15);
+  const int gi = 16 * ti + 4 * (q & 3) + (threadIdx.x >> 4), gj = 16 * tj + (threadIdx.x & 15);
   if (!(gi < d.B && gj < d.B && gi >= gj)) return;
   const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
   double m2 = d.m2_in[e];
+#pragma unroll 4
   for (int b = 0; b < d.nblk; ++b) {
     const double nb = (double)blk_lines_of(d, b) * d.S;
     const int ksb = ks_of(d, b);
@@ -246,17 +622,27 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const r
                                        const rxk::LaunchSet* ls2, int wg2, hipStream_t st) {
   using namespace rxk;
   if (phase == 2) {
-    if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(NT), 0, st, *ls);
+    if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(MB), 0, st, *ls);
     if (wg2 > 0) {
-      if (prec == P_F64) hipLaunchKernelGGL((k_merge_mat<double>), dim3(wg2), dim3(NT), 0, st, *ls2);
-      else hipLaunchKernelGGL((k_merge_mat<float>), dim3(wg2), dim3(NT), 0, st, *ls2);
+      if (prec == P_F64) hipLaunchKernelGGL((k_merge_mat<double>), dim3(wg2), dim3(MB), 0, st, *ls2);
+      else hipLaunchKernelGGL((k_merge_mat<float>), dim3(wg2), dim3(MB), 0, st, *ls2);
     }
     return hipGetLastError();
   }
   if (wg <= 0) return hipSuccess;
+  if (phase == 1 && in_type == IN_U16 && (prec == P_BF16 || prec == P_F16)) {
+    bool aligned = true;
+    for (int i = 0; i < ls->nb; ++i) aligned = aligned && ls->d[i].vec_ok;
+    if (aligned) {
+      if (prec == P_BF16) hipLaunchKernelGGL((k_syrk3<P_BF16>), dim3(wg), dim3(S2NT), 0, st, *ls);
+      else hipLaunchKernelGGL((k_syrk3<P_F16>), dim3(wg), dim3(S2NT), 0, st, *ls);
+      return hipGetLastError();
+    }
+  }
 #define RXK_CASE(INV, PV)                                                                      \
   if (in_type == INV && prec == PV) {                                                          \
     if (phase == 0) hipLaunchKernelGGL((k_shift<INV, PV>), dim3(wg), dim3(NT), 0, st, *ls);    \
+    else if (MM<PV>::KV == 8) hipLaunchKernelGGL((k_syrk2<INV, (MM<PV>::KV == 8 ? PV : P_BF16)>), dim3(wg), dim3(S2NT), 0, st, *ls); \
     else hipLaunchKernelGGL((k_syrk<INV, PV>), dim3(wg), dim3(NT), 0, st, *ls);                \
     return hipGetLastError();                                                                  \
   }

@@ -15,6 +15,9 @@
 //    (16 consecutive samples of one band per lane group, coalesced).
 #include "rx_dev.h"
 
+#include <algorithm>
+#include <climits>
+
 namespace rxk {
 
 constexpr int MAXBW = 16 * MAXT;    // 320: padded band pitch of the whitening operand
@@ -151,6 +154,230 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
   if (kg == 0 && 16 * w + n < nvalid) {
     if constexpr (F64OUT) static_cast<double*>(d.scores)[out0 + 16 * w + n] = dl;
     else static_cast<float*>(d.scores)[out0 + 16 * w + n] = dl;
+  }
+}
+
+// ---------------------------------------------------------------------------- whitening, 16-bit input
+// k_whiten2: the same score for 16-bit integer input and the 8-value operand
+// formats, organised for operand reuse.
+//  * One workgroup per CU walks an even share of the launch's 32-pixel tiles
+//    (32 consecutive samples of one line).  The whitening operand of the
+//    current block sits in LDS in matrix-core operand order (lane-major
+//    fragments of 16 bytes, or 8 for FP8), staged once per block the
+//    workgroup touches, together with the split mean, band and row scales.
+//  * A wave owns a whole tile: lane (n, kg) loads sample pair 2n, 2n+1 of
+//    bands 32s + 8kg + j as one dword, so the even samples form the operand
+//    columns of one 16-pixel product and the odd samples of another; both
+//    reuse every operand fragment read from LDS.  The centred, scaled and
+//    rounded tile stays in registers (two waves per SIMD overlap one wave's
+//    loads with the other's products).  No workgroup barrier inside a
+//    block.
+//  * Arithmetic is that of k_whiten: centring in FP32 with the mean split
+//    hi + lo, the band's power-of-two scale, one rounding to the operand
+//    format, FP32 accumulation, the row scale on the output, squares summed
+//    over tile rows then over the four lane groups.
+constexpr int W2NT = 512;                     // 8 waves
+constexpr int W2W = W2NT / 64;
+constexpr int W2TP = 32;                      // pixels per tile
+constexpr int MAXS = (MAXT + 1) / 2;          // 32-band operand steps
+constexpr int MAXFR = (MAXT / 2) * (MAXT / 2 + 1) + ((MAXT & 1) ? (MAXT / 2 + 1) : 0);
+
+// Operand fragments before out-band tile i: sum over m = 1..i of ceil(m / 2)
+// (tile i spans the in-band steps 0..i/2 of the lower triangle).
+__host__ __device__ constexpr int fr_off(int i) {
+  return (i / 2) * (i / 2 + 1) + ((i & 1) ? (i / 2 + 1) : 0);
+}
+static_assert(fr_off(MAXT) == MAXFR, "fragment count");
+
+template <int P> __device__ __forceinline__ typename MM<P>::frag pack_frag(const typename MM<P>::storage e[8]);
+template <> __device__ __forceinline__ bf16x8 pack_frag<P_BF16>(const uint16_t e[8]) {
+  uint4 w;
+  pack8(e, &w);
+  return __builtin_bit_cast(bf16x8, w);
+}
+template <> __device__ __forceinline__ f16x8 pack_frag<P_F16>(const uint16_t e[8]) {
+  uint4 w;
+  pack8(e, &w);
+  return __builtin_bit_cast(f16x8, w);
+}
+template <> __device__ __forceinline__ long pack_frag<P_FP8>(const uint8_t e[8]) {
+  const uint2 w{(uint32_t)e[0] | ((uint32_t)e[1] << 8) | ((uint32_t)e[2] << 16) | ((uint32_t)e[3] << 24),
+                (uint32_t)e[4] | ((uint32_t)e[5] << 8) | ((uint32_t)e[6] << 16) | ((uint32_t)e[7] << 24)};
+  return __builtin_bit_cast(long, w);
+}
+
+// ls.wg0 holds the prefix of 32-pixel tiles per batch (not workgroups).  NS
+// is the number of 32-band steps, ceil(nT / 2), the same for every batch of
+// the launch.
+template <int P, int NS>
+__global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t ntile_all) {
+  using M = MM<P>;
+  using S = typename M::storage;
+  using F = typename M::frag;
+  constexpr int FB = 8 * (int)sizeof(S);       // operand bytes per lane
+  __shared__ __attribute__((aligned(16))) uint8_t wf[MAXFR * 64 * FB];
+  __shared__ __attribute__((aligned(16))) float mhs[16 * MAXT];
+  __shared__ __attribute__((aligned(16))) float mls[16 * MAXT];
+  __shared__ __attribute__((aligned(16))) float iss[16 * MAXT];
+  __shared__ __attribute__((aligned(16))) float oss[16 * MAXT];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = lane & 15, kg = lane >> 4;
+  const int64_t T0 = ntile_all * blockIdx.x / gridDim.x, T1 = ntile_all * (blockIdx.x + 1) / gridDim.x;
+
+  for (int64_t cur = T0; cur < T1;) {
+    // locate (batch, block) of tile cur and the end of this block's share
+    int bi = 0;
+    while (bi + 1 < ls.nb && cur >= ls.wg0[bi + 1]) ++bi;
+    const BatchDesc& d = ls.d[bi];
+    const int B = d.B, Bp = d.Bp, nT = Bp / 16, Sm = d.S;
+    const int tpl = (Sm + W2TP - 1) / W2TP;
+    const int64_t tl = cur - ls.wg0[bi];                       // tile within the batch
+    const int64_t tpb = (int64_t)d.blk_lines * tpl;            // tiles per (full) block
+    const int b = (int)min(tl / tpb, (int64_t)d.nblk - 1);
+    const int64_t blk_end = ls.wg0[bi] + (int64_t)b * tpb + (int64_t)blk_lines_of(d, b) * tpl;
+    const int64_t seg_end = min(T1, blk_end);
+    const int64_t tb0 = cur - ls.wg0[bi];                      // segment, batch-relative tiles
+    const int nseg = (int)(seg_end - cur);
+    cur = seg_end;
+    float* out = static_cast<float*>(d.scores);
+
+    if (d.status[b] != 0) {                                     // singular / not ready: NaN scores
+      for (int q = tid; q < nseg * W2TP; q += W2NT) {
+        const int64_t t = tb0 + q / W2TP;
+        const int smp = W2TP * (int)(t % tpl) + q % W2TP;
+        if (smp < Sm) out[(t / tpl) * Sm + smp] = __builtin_nanf("");
+      }
+      continue;
+    }
+
+    __syncthreads();                                            // previous segment's readers are done
+    {
+      const S* wl = static_cast<const S*>(d.wlp) + (int64_t)b * Bp * Bw;
+      const int nfr = fr_off(nT);
+      for (int it = tid; it < nfr * 64; it += W2NT) {
+        const int f = it >> 6, l = it & 63;
+        int i = 0;
+        while (fr_off(i + 1) <= f) ++i;
+        const int st = f - fr_off(i);
+        const S* src = wl + (int64_t)(16 * i + (l & 15)) * Bw + 32 * st + 8 * (l >> 4);
+        if constexpr (FB == 16) *reinterpret_cast<uint4*>(wf + it * 16) = *reinterpret_cast<const uint4*>(src);
+        else *reinterpret_cast<uint2*>(wf + it * 8) = *reinterpret_cast<const uint2*>(src);
+      }
+      const double* mu = d.mu_snap + (int64_t)b * Bp;
+      const float* isc = d.iscale + (int64_t)b * Bp;
+      const float* osc = d.oscale + (int64_t)b * Bp;
+      for (int k = tid; k < 16 * MAXT; k += W2NT) {
+        float mh = 0.0f, ml = 0.0f, is = 0.0f;
+        if (k < B) {
+          const double m = mu[k];
+          mh = (float)m;
+          ml = (float)(m - (double)mh);
+          is = isc[k];
+        }
+        mhs[k] = mh;
+        mls[k] = ml;
+        iss[k] = is;                                            // zero past the band count
+        oss[k] = k < Bp ? osc[k] : 0.0f;
+      }
+    }
+    __syncthreads();
+
+    const uint16_t* xb = static_cast<const uint16_t*>(d.x);
+    uint32_t raw[NS][8];
+    // Only the last 32-band step can reach past the band count (the earlier
+    // steps end at or below 16 (nT - 1) < B); its rows are clamped to B - 1
+    // and zeroed by the band scale.  The earlier steps walk a running row
+    // pointer so no per-load offsets stay live across tiles.
+    auto load_raw = [&](int64_t t) {
+      const int64_t line = t / tpl;
+      const int smp = W2TP * (int)(t % tpl) + 2 * n;
+      const uint16_t* xl = xb + line * B * Sm + (smp < Sm ? smp : 0);
+      const uint16_t* q = xl + (int64_t)(8 * kg) * Sm;
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        if (st + 1 < NS) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            raw[st][j] = *reinterpret_cast<const uint32_t*>(q);
+            q += Sm;
+            asm volatile("" : "+v"(q));
+          }
+          q += (int64_t)24 * Sm;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int k = min(32 * st + 8 * kg + j, B - 1);
+            raw[st][j] = *reinterpret_cast<const uint32_t*>(xl + (int64_t)k * Sm);
+          }
+        }
+      }
+    };
+
+    int64_t t = tb0 + wv;
+    const int64_t tend = tb0 + nseg;
+    for (; t < tend; t += W2W) {
+      load_raw(t);
+      const int smp = W2TP * (int)(t % tpl) + 2 * n;
+      const bool ok = smp < Sm;
+      F xf0[NS], xf1[NS];
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        {
+          // re-read per tile: hoisting these tile-invariant values would hold
+          // 24 registers per step for the whole loop
+          int k0 = 32 * st + 8 * kg;
+          asm volatile("" : "+v"(k0));
+          const float4 mh0 = *reinterpret_cast<const float4*>(&mhs[k0]);
+          const float4 mh1 = *reinterpret_cast<const float4*>(&mhs[k0 + 4]);
+          const float4 ml0 = *reinterpret_cast<const float4*>(&mls[k0]);
+          const float4 ml1 = *reinterpret_cast<const float4*>(&mls[k0 + 4]);
+          const float4 is0 = *reinterpret_cast<const float4*>(&iss[k0]);
+          const float4 is1 = *reinterpret_cast<const float4*>(&iss[k0 + 4]);
+          const float mh[8] = {mh0.x, mh0.y, mh0.z, mh0.w, mh1.x, mh1.y, mh1.z, mh1.w};
+          const float ml[8] = {ml0.x, ml0.y, ml0.z, ml0.w, ml1.x, ml1.y, ml1.z, ml1.w};
+          const float is[8] = {is0.x, is0.y, is0.z, is0.w, is1.x, is1.y, is1.z, is1.w};
+          S e0[8], e1[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float c0 = (((float)(raw[st][j] & 0xffffu) - mh[j]) - ml[j]) * is[j];
+            const float c1 = (((float)(raw[st][j] >> 16) - mh[j]) - ml[j]) * is[j];
+            e0[j] = to_storage<P>(ok ? c0 : 0.0f);
+            e1[j] = to_storage<P>(ok ? c1 : 0.0f);
+          }
+          xf0[st] = pack_frag<P>(e0);
+          xf1[st] = pack_frag<P>(e1);
+        }
+      }
+
+      float dl0 = 0.0f, dl1 = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 2 * NS; ++i) {
+        if (i < 2 * NS - 1 || i < nT) {
+          typename M::acc a0{}, a1{};
+#pragma unroll
+          for (int st = 0; st <= i / 2; ++st) {
+            const F af = *reinterpret_cast<const F*>(wf + ((fr_off(i) + st) * 64 + lane) * FB);
+            a0 = M::mma(af, xf0[st], a0);
+            a1 = M::mma(af, xf1[st], a1);
+          }
+          const float4 os = *reinterpret_cast<const float4*>(&oss[16 * i + 4 * kg]);
+          const float o4[4] = {os.x, os.y, os.z, os.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float y0 = a0[j] * o4[j], y1 = a1[j] * o4[j];
+            dl0 += y0 * y0;
+            dl1 += y1 * y1;
+          }
+        }
+      }
+      dl0 += __shfl_xor(dl0, 16, 64);
+      dl0 += __shfl_xor(dl0, 32, 64);
+      dl1 += __shfl_xor(dl1, 16, 64);
+      dl1 += __shfl_xor(dl1, 32, 64);
+      if (kg == 0 && ok) *reinterpret_cast<float2*>(&out[(t / tpl) * Sm + smp]) = float2{dl0, dl1};
+    }
   }
 }
 
@@ -296,6 +523,48 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
                                         hipStream_t st) {
   using namespace rxk;
   if (wg <= 0) return hipSuccess;
+  if (in_type == IN_U16 && (wprec == P_BF16 || wprec == P_F16 || wprec == P_FP8)) {
+    // 16-bit rows with an even sample count and 4-byte aligned base take the
+    // tile kernel (the 16-byte alignment of vec_ok implies both)
+    bool ok = true;
+    for (int i = 0; i < ls->nb; ++i) ok = ok && ls->d[i].vec_ok && (ls->d[i].S % 2 == 0);
+    if (ok) {
+      LaunchSet t = *ls;
+      t.wg0[0] = 0;
+      for (int i = 0; i < ls->nb; ++i) {
+        const BatchDesc& d = ls->d[i];
+        const int64_t tpl = (d.S + W2TP - 1) / W2TP;
+        const int64_t tiles = ((int64_t)(d.nblk - 1) * d.blk_lines + d.last_lines) * tpl;
+        if ((int64_t)t.wg0[i] + tiles > INT32_MAX) { ok = false; break; }
+        t.wg0[i + 1] = t.wg0[i] + (int)tiles;
+      }
+      if (ok) {
+        static int cus[64] = {0};
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+        if (dev < 64 && cus[dev] == 0) {
+          int c = 0;
+          if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipGetLastError();
+          cus[dev] = c;
+        }
+        const int ncu = (dev < 64 && cus[dev] > 0) ? cus[dev] : 256;
+        const int64_t ntile = t.wg0[ls->nb];
+        const int g = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, ntile / (2 * W2W)));
+        const int ns = Bw / 32;                                  // the launch shares Bw = 32 ceil(nT / 2)
+        switch (wprec * 16 + ns) {
+#define RXK_W2(PV, N)                                                                                 \
+  case PV * 16 + N: hipLaunchKernelGGL((k_whiten2<PV, N>), dim3(g), dim3(W2NT), 0, st, t, Bw, ntile); break;
+#define RXK_W2P(PV) RXK_W2(PV, 1) RXK_W2(PV, 2) RXK_W2(PV, 3) RXK_W2(PV, 4) RXK_W2(PV, 5) \
+                    RXK_W2(PV, 6) RXK_W2(PV, 7) RXK_W2(PV, 8) RXK_W2(PV, 9) RXK_W2(PV, 10)
+          RXK_W2P(P_BF16) RXK_W2P(P_F16) RXK_W2P(P_FP8)
+#undef RXK_W2P
+#undef RXK_W2
+          default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+      }
+    }
+  }
 #define RXK_W(INV, PV)                                                                          \
   if (in_type == INV && wprec == PV) {                                                          \
     hipLaunchKernelGGL((k_whiten<INV, PV>), dim3(wg), dim3(NT), 0, st, *ls, Bw);                \

@@ -110,6 +110,7 @@ __device__ __forceinline__ uint8_t f32_to_e4m3(float f) {
 }
 
 template <int P> __device__ __forceinline__ typename MM<P>::storage to_storage(float v);
+template <> __device__ __forceinline__ double to_storage<P_F64>(float v) { return v; }
 template <> __device__ __forceinline__ float to_storage<P_F32>(float v) { return v; }
 template <> __device__ __forceinline__ uint16_t to_storage<P_BF16>(float v) { return f32_to_bf16_bits(v); }
 template <> __device__ __forceinline__ uint16_t to_storage<P_F16>(float v) { return f32_to_f16_bits(v); }
@@ -156,6 +157,43 @@ __device__ __forceinline__ void load8(const double* p, double v[8]) {
   }
 }
 
+// Eight input values <-> 16-byte words, in registers (no memory round trip).
+__device__ __forceinline__ void unpack8(const uint4* w, uint16_t v[8]) {
+  v[0] = w[0].x & 0xffff; v[1] = w[0].x >> 16; v[2] = w[0].y & 0xffff; v[3] = w[0].y >> 16;
+  v[4] = w[0].z & 0xffff; v[5] = w[0].z >> 16; v[6] = w[0].w & 0xffff; v[7] = w[0].w >> 16;
+}
+__device__ __forceinline__ void pack8(const uint16_t v[8], uint4* w) {
+  w[0] = uint4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+               (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
+}
+__device__ __forceinline__ void unpack8(const uint4* w, float v[8]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    v[4 * i] = __builtin_bit_cast(float, w[i].x); v[4 * i + 1] = __builtin_bit_cast(float, w[i].y);
+    v[4 * i + 2] = __builtin_bit_cast(float, w[i].z); v[4 * i + 3] = __builtin_bit_cast(float, w[i].w);
+  }
+}
+__device__ __forceinline__ void pack8(const float v[8], uint4* w) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    w[i] = uint4{__builtin_bit_cast(uint32_t, v[4 * i]), __builtin_bit_cast(uint32_t, v[4 * i + 1]),
+                 __builtin_bit_cast(uint32_t, v[4 * i + 2]), __builtin_bit_cast(uint32_t, v[4 * i + 3])};
+}
+__device__ __forceinline__ void unpack8(const uint4* w, double v[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[2 * i] = __builtin_bit_cast(double, uint2{w[i].x, w[i].y});
+    v[2 * i + 1] = __builtin_bit_cast(double, uint2{w[i].z, w[i].w});
+  }
+}
+__device__ __forceinline__ void pack8(const double v[8], uint4* w) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint2 a = __builtin_bit_cast(uint2, v[2 * i]), b = __builtin_bit_cast(uint2, v[2 * i + 1]);
+    w[i] = uint4{a.x, a.y, b.x, b.y};
+  }
+}
+
 // ------------------------------------------------------------------ wave reductions
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -180,6 +218,8 @@ struct BatchDesc {
   int ks, ks_last;        // covariance split count per block / for the last block
   int nsr, nsup;          // super-rows ceil(Bp/64); lower super-tiles nsr(nsr+1)/2
   int vec_ok;             // 16-byte vector loads of input rows are aligned
+  int nrect;              // covariance rectangles (16-tile units) owned by the waves of one workgroup
+  uint8_t rect[16][4];    // per wave: first tile row, first tile column, tile rows, tile columns
   int ddof;
   double rho;             // ridge: lambda = rho * tr(Sigma) / B
   uint64_t reset_bits;    // bit b: block b starts a new statistics window

@@ -85,14 +85,54 @@ static void dev_free(DevBuf& b) {
 
 // ---------------------------------------------------------------------------- geometry
 static constexpr uint32_t kMagic = 0x52585354u;   // "RXST"
-static constexpr int kSplitChunks = 64;            // pixel chunks per covariance split (4096 px)
+static constexpr int kSplitChunks = 64;            // pixel chunks per covariance split, 64x64 super-tile kernel
+static constexpr int kSplitChunks2 = 80;           // pixel chunks per covariance split, whole-triangle kernel
 static constexpr int kMaxBlocksPerBatch = 64;      // reset bits are a 64-bit mask
 
 static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 static int pad16(int b) { return 16 * ceil_div(b, 16); }
 static int pad32(int b) { return 32 * ceil_div(b, 32); }
 static size_t in_elem_size(int t) { return t == RX_IN_U16 ? 2 : (t == RX_IN_F32 ? 4 : 8); }
-static int splits_for(int lines, int cpl) { return std::min(64, std::max(1, ceil_div((int64_t)lines * cpl, kSplitChunks))); }
+// Splits depend only on the block (never on the batch), so a block's result
+// is the same alone and in any batch.
+static bool whole_triangle(int sp) { return sp == RX_BF16 || sp == RX_FP16; }
+static int splits_for(int lines, int cpl, int sp) {
+  const int per = whole_triangle(sp) ? kSplitChunks2 : kSplitChunks;
+  return std::min(64, std::max(1, ceil_div((int64_t)lines * cpl, per)));
+}
+
+// Rectangles of at most 4 x 4 16-band tiles covering the lower triangle of
+// T x T tiles (bands of 4 tile rows cut into 4-column pieces: at most 15
+// for T <= 20), assigned to waves so the four SIMDs of a CU get similar work.
+static int make_rects(int T, uint8_t rect[16][4]) {
+  struct Rc { int r0, c0, nr, nc, n; };
+  std::vector<Rc> v;
+  for (int r0 = 0; r0 < T; r0 += 4) {
+    const int nr = std::min(4, T - r0), ncols = r0 + nr;
+    for (int c0 = 0; c0 < ncols; c0 += 4) {
+      const int nc = std::min(4, ncols - c0);
+      int n = 0;
+      for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nc; ++j) n += (r0 + i >= c0 + j);
+      if (n > 0) v.push_back(Rc{r0, c0, nr, nc, n});
+    }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const Rc& a, const Rc& b) { return a.n > b.n; });
+  int load[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+  std::memset(rect, 0, 16 * 4);
+  int nw = 0;
+  for (const Rc& r : v) {
+    int best = 0;
+    for (int q = 1; q < 4; ++q)
+      if (cnt[q] < 4 && (cnt[best] >= 4 || load[q] < load[best])) best = q;
+    const int w = best + 4 * cnt[best];
+    rect[w][0] = (uint8_t)r.r0; rect[w][1] = (uint8_t)r.c0; rect[w][2] = (uint8_t)r.nr; rect[w][3] = (uint8_t)r.nc;
+    load[best] += r.n;
+    cnt[best] += 1;
+    nw = std::max(nw, w + 1);
+  }
+  return nw;
+}
 
 struct Block {
   int64_t line0;   // first line within the push
@@ -107,7 +147,7 @@ struct Sizes {
 static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
   const int Bp = pad16(B), Bw = pad32(Bp);
   const int nsr = ceil_div(Bp, SUP), nsup = nsr * (nsr + 1) / 2;
-  const int ks = splits_for(blk_lines, ceil_div(S, KC));
+  const int ks = splits_for(blk_lines, ceil_div(S, KC), sp);
   const size_t psz = sp == RX_FP64 ? 8 : 4;
   Sizes z;
   z.shift = (size_t)nblk * Bp * 8;
@@ -278,8 +318,13 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   if ((r = dev_ensure(s->mu, z.mu, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->m2s, z.m2, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->nsnap, z.nsnap, s->st)) != RX_OK) return r;
+  // the factor never writes above the diagonal tiles of W or its low-precision
+  // copy (nor the copy's padding columns): those stay as zeroed here
+  const size_t w_before = s->w64.cap, wl_before = s->wlp.cap;
   if ((r = dev_ensure(s->w64, z.w64, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->wlp, z.wlp, s->st)) != RX_OK) return r;
+  if (s->w64.cap != w_before) HIPC(hipMemsetAsync(s->w64.p, 0, s->w64.cap, s->st));
+  if (s->wlp.cap != wl_before) HIPC(hipMemsetAsync(s->wlp.p, 0, s->wlp.cap, s->st));
   if ((r = dev_ensure(s->isc, z.scl, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->osc, z.scl, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->status, z.status, s->st)) != RX_OK) return r;
@@ -450,8 +495,9 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.blk_lines = L;
   d.last_lines = last;
   d.cpl = s->cpl;
-  d.ks = splits_for(L, s->cpl);
-  d.ks_last = splits_for(last, s->cpl);
+  d.ks = splits_for(L, s->cpl, s->sp);
+  d.ks_last = splits_for(last, s->cpl, s->sp);
+  d.nrect = make_rects(s->Bp / 16, d.rect);
   d.nsr = ceil_div(s->Bp, SUP);
   d.nsup = d.nsr * (d.nsr + 1) / 2;
   d.vec_ok = ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0) && (((size_t)s->S * s->esz) % 16 == 0);
@@ -499,9 +545,9 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.wp = s->wp;
   j.Bw = s->Bw;
   j.wg_shift = nblk * (s->Bp / 4);
-  j.wg_syrk = d.nsup * ((nblk - 1) * d.ks + d.ks_last);
-  j.wg_merge = 1;
-  j.wg_mmat = (s->Bp / 16) * (s->Bp / 16 + 1) / 2;
+  j.wg_syrk = (whole_triangle(s->sp) ? 1 : d.nsup) * ((nblk - 1) * d.ks + d.ks_last);
+  j.wg_merge = ceil_div(s->Bp, 64);
+  j.wg_mmat = 4 * (s->Bp / 16) * (s->Bp / 16 + 1) / 2;
   j.wg_factor = nblk;
   j.wg_whiten = (int)(lines * s->cpl);
 

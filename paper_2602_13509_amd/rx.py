@@ -151,13 +151,22 @@ class RxStream:
 
     # -- core path
     def rx_push_lines(self, lines, stream=None, allow_notready=True) -> int:
-        """lines: BIL [n_lines][B][S] torch tensor (device or host) or numpy array."""
+        """lines: BIL [n_lines][B][S] torch tensor (device or host) or numpy array.
+
+        A device tensor is read asynchronously by the library's own HIP
+        stream; the caller's stream (torch's current one by default) is then
+        made to wait for that work (rx_wait, no host block), so later work on
+        it -- including torch's reuse of the tensor's memory once it is
+        freed -- cannot overwrite the lines before they are read."""
         n = lines.shape[0]
         assert tuple(lines.shape[1:]) == (self.B, self.S), lines.shape
         dev = _is_dev(lines)
         sh = _stream_handle(stream) if dev else 0
-        return check(LIB.rx_push_lines(self.h, _ptr(lines), n, dev, sh),
-                     allow=(RX_E_NOTREADY,) if allow_notready else ())
+        r = check(LIB.rx_push_lines(self.h, _ptr(lines), n, dev, sh),
+                  allow=(RX_E_NOTREADY,) if allow_notready else ())
+        if dev:
+            check(LIB.rx_wait(self.h, sh))
+        return r
 
     def rx_scores(self, out, stream=None) -> int:
         n = C.c_int64()

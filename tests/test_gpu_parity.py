@@ -298,3 +298,30 @@ def test_determinism_bitwise(rxm):
     a = run_stream(rxm, cube, "bf16", "bf16", block_lines=10, ridge_rel=1e-6).scores_host()
     b = run_stream(rxm, cube, "bf16", "bf16", block_lines=10, ridge_rel=1e-6).scores_host()
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8"])
+def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt):
+    # 16-bit rows with 16-byte aligned starts take the 32-pixel tile kernel;
+    # the same lines pushed from a buffer offset by one element take the
+    # chunk kernel.  Both centre, scale and round identically and run the same
+    # matrix-core chains, so with FP64 statistics (computed identically on
+    # both routes) the scores must match bit for bit.  S = 200 leaves a
+    # ragged last tile; 3 blocks put block boundaries inside workgroup ranges.
+    import torch
+    B, S = 270, 200
+    cube = synth.sensor_cube(26, lines=90, samples=S, bands=B).cube
+    say(f"tile vs chunk whitening {fmt}: 90x{S}x{B} u16, blocks of 40")
+    a = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten=fmt, block_lines=40))
+    a.rx_push_lines(dev(cube))
+    flat = torch.empty(cube.size + 1, dtype=torch.int16, device="cuda")
+    flat[1:].copy_(dev(cube.view(np.int16).reshape(-1)))
+    off = flat[1:]
+    assert off.data_ptr() % 16 == 2
+    b = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten=fmt, block_lines=40))
+    b.rx_push_lines(off.view(cube.shape))   # same bits; the library reads them as uint16
+    a.rx_sync()
+    b.rx_sync()
+    sa, sb = a.scores_host(), b.scores_host()
+    assert np.all(np.isfinite(sa))
+    assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))
