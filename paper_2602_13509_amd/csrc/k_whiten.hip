@@ -145,7 +145,8 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
       for (int j = 0; j < 4; ++j) {
         A y = acc[i][j];
         if constexpr (M::KV == 8) y *= osc[16 * i + M::out_row(kg, j)];
-        dl += y * y;
+        if constexpr (sizeof(A) == 4) dl = __builtin_fmaf(y, y, dl);
+        else dl = __builtin_fma(y, y, dl);
       }
     }
   }
@@ -160,25 +161,25 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
 // ---------------------------------------------------------------------------- whitening, 16-bit input
 // k_whiten2: the same score for 16-bit integer input and the 8-value operand
 // formats, organised for operand reuse.
-//  * One workgroup per CU walks an even share of the launch's 32-pixel tiles
-//    (32 consecutive samples of one line).  The whitening operand of the
+//  * One workgroup per CU walks an even share of the launch's tiles of 16 G
+//    pixels (consecutive samples of one line).  The whitening operand of the
 //    current block sits in LDS in matrix-core operand order (lane-major
 //    fragments of 16 bytes, or 8 for FP8), staged once per block the
 //    workgroup touches, together with the split mean, band and row scales.
-//  * A wave owns a whole tile: lane (n, kg) loads sample pair 2n, 2n+1 of
-//    bands 32s + 8kg + j as one dword, so the even samples form the operand
-//    columns of one 16-pixel product and the odd samples of another; both
-//    reuse every operand fragment read from LDS.  The centred, scaled and
-//    rounded tile stays in registers (two waves per SIMD overlap one wave's
-//    loads with the other's products).  No workgroup barrier inside a
-//    block.
+//  * A wave owns a whole tile: lane (n, kg) loads samples G n .. G n + G - 1
+//    of bands 32 s + 8 kg + j in one load, so sample G n + g is column n of
+//    the g-th 16-pixel product; all G products reuse every operand fragment
+//    read from LDS (and every band constant).  The centred, scaled and
+//    rounded tile stays in registers; the waves of a SIMD overlap one
+//    another's loads and products.  No workgroup barrier inside a block.
 //  * Arithmetic is that of k_whiten: centring in FP32 with the mean split
 //    hi + lo, the band's power-of-two scale, one rounding to the operand
 //    format, FP32 accumulation, the row scale on the output, squares summed
 //    over tile rows then over the four lane groups.
 constexpr int W2NT = 512;                     // 8 waves
 constexpr int W2W = W2NT / 64;
-constexpr int W2TP = 32;                      // pixels per tile
+constexpr int W2G = 4;                        // 16-pixel products per tile
+constexpr int W2TP = 16 * W2G;                // pixels per tile
 constexpr int MAXS = (MAXT + 1) / 2;          // 32-band operand steps
 constexpr int MAXFR = (MAXT / 2) * (MAXT / 2 + 1) + ((MAXT & 1) ? (MAXT / 2 + 1) : 0);
 
@@ -206,19 +207,76 @@ template <> __device__ __forceinline__ long pack_frag<P_FP8>(const uint8_t e[8])
   return __builtin_bit_cast(long, w);
 }
 
-// ls.wg0 holds the prefix of 32-pixel tiles per batch (not workgroups).  NS
-// is the number of 32-band steps, ceil(nT / 2), the same for every batch of
-// the launch.
-template <int P, int NS>
+// Round two FP32 values to the operand format (RNE) and pack them, low
+// value first.  BF16 and FP16 convert both in one instruction.
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
+template <int P> __device__ __forceinline__ uint32_t cvt_pack2(float a, float b);
+template <> __device__ __forceinline__ uint32_t cvt_pack2<P_BF16>(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+template <> __device__ __forceinline__ uint32_t cvt_pack2<P_F16>(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
+}
+// Eight centred values -> one operand fragment.
+template <int P> __device__ __forceinline__ typename MM<P>::frag cvt_frag(const float c[8]) {
+  if constexpr (P == P_FP8) {
+    uint8_t e[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = f32_to_e4m3(c[j]);
+    return pack_frag<P_FP8>(e);
+  } else {
+    const uint4 w{cvt_pack2<P>(c[0], c[1]), cvt_pack2<P>(c[2], c[3]), cvt_pack2<P>(c[4], c[5]),
+                  cvt_pack2<P>(c[6], c[7])};
+    return __builtin_bit_cast(typename MM<P>::frag, w);
+  }
+}
+
+// G consecutive 16-bit samples of one band row, as loaded.
+template <int G> struct Raw;
+template <> struct Raw<2> {
+  uint32_t w;
+  __device__ __forceinline__ void load(const char* p) { w = *reinterpret_cast<const uint32_t*>(p); }
+  __device__ __forceinline__ uint32_t at(int g) const { return g ? (w >> 16) : (w & 0xffffu); }
+};
+template <> struct Raw<4> {
+  uint2 w;
+  __device__ __forceinline__ void load(const char* p) { w = *reinterpret_cast<const uint2*>(p); }
+  __device__ __forceinline__ uint32_t at(int g) const {
+    const uint32_t v = g < 2 ? w.x : w.y;
+    return (g & 1) ? (v >> 16) : (v & 0xffffu);
+  }
+};
+template <int G> __device__ __forceinline__ void store_scores(float* p, const float* v);
+template <> __device__ __forceinline__ void store_scores<2>(float* p, const float* v) {
+  *reinterpret_cast<float2*>(p) = float2{v[0], v[1]};
+}
+template <> __device__ __forceinline__ void store_scores<4>(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = float4{v[0], v[1], v[2], v[3]};
+}
+
+// Pixel groups per tile: four where the operand tile fits the register
+// budget without spilling (16-bit operands up to 288 bands, FP8 up to 192),
+// two otherwise.
+__host__ __device__ constexpr int w2_groups(int p, int ns) {
+  return (p == P_FP8) ? (ns <= 6 ? 4 : 2) : (ns <= 9 ? 4 : 2);
+}
+
+// ls.wg0 holds the prefix of tiles per batch (not workgroups).  NS is the
+// number of 32-band steps, ceil(nT / 2), the same for every batch of the
+// launch.  Requires S % 8 == 0 and 16-byte aligned rows (vec_ok).
+template <int P, int NS, int G>
 __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t ntile_all) {
   using M = MM<P>;
   using S = typename M::storage;
   using F = typename M::frag;
+  constexpr int TP = 16 * G;                   // pixels per tile
   constexpr int FB = 8 * (int)sizeof(S);       // operand bytes per lane
   __shared__ __attribute__((aligned(16))) uint8_t wf[MAXFR * 64 * FB];
-  __shared__ __attribute__((aligned(16))) float mhs[16 * MAXT];
-  __shared__ __attribute__((aligned(16))) float mls[16 * MAXT];
-  __shared__ __attribute__((aligned(16))) float iss[16 * MAXT];
+  __shared__ __attribute__((aligned(16))) float nqh[16 * MAXT];   // -(mean hi) * band scale
+  __shared__ __attribute__((aligned(16))) float nql[16 * MAXT];   // -(mean lo) * band scale
+  __shared__ __attribute__((aligned(16))) float iss[16 * MAXT];   // band scale 2^-e
   __shared__ __attribute__((aligned(16))) float oss[16 * MAXT];
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -232,7 +290,7 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
     while (bi + 1 < ls.nb && cur >= ls.wg0[bi + 1]) ++bi;
     const BatchDesc& d = ls.d[bi];
     const int B = d.B, Bp = d.Bp, nT = Bp / 16, Sm = d.S;
-    const int tpl = (Sm + W2TP - 1) / W2TP;
+    const int tpl = (Sm + TP - 1) / TP;
     const int64_t tl = cur - ls.wg0[bi];                       // tile within the batch
     const int64_t tpb = (int64_t)d.blk_lines * tpl;            // tiles per (full) block
     const int b = (int)min(tl / tpb, (int64_t)d.nblk - 1);
@@ -244,9 +302,9 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
     float* out = static_cast<float*>(d.scores);
 
     if (d.status[b] != 0) {                                     // singular / not ready: NaN scores
-      for (int q = tid; q < nseg * W2TP; q += W2NT) {
-        const int64_t t = tb0 + q / W2TP;
-        const int smp = W2TP * (int)(t % tpl) + q % W2TP;
+      for (int q = tid; q < nseg * TP; q += W2NT) {
+        const int64_t t = tb0 + q / TP;
+        const int smp = TP * (int)(t % tpl) + q % TP;
         if (smp < Sm) out[(t / tpl) * Sm + smp] = __builtin_nanf("");
       }
       continue;
@@ -262,8 +320,25 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
         while (fr_off(i + 1) <= f) ++i;
         const int st = f - fr_off(i);
         const S* src = wl + (int64_t)(16 * i + (l & 15)) * Bw + 32 * st + 8 * (l >> 4);
-        if constexpr (FB == 16) *reinterpret_cast<uint4*>(wf + it * 16) = *reinterpret_cast<const uint4*>(src);
-        else *reinterpret_cast<uint2*>(wf + it * 8) = *reinterpret_cast<const uint2*>(src);
+        if constexpr (P == P_BF16) {
+          // BF16 keeps FP32's exponent range, so the row's power-of-two output
+          // scale folds into the staged operand exactly; the products then
+          // come out already scaled (bit for bit what scaling them would give)
+          const float o = d.oscale[(int64_t)b * Bp + 16 * i + (l & 15)];
+          uint4 w = *reinterpret_cast<const uint4*>(src);
+          uint32_t* q = reinterpret_cast<uint32_t*>(&w);
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const float lo = __builtin_bit_cast(float, q[h] << 16) * o;
+            const float hi = __builtin_bit_cast(float, q[h] & 0xffff0000u) * o;
+            q[h] = (__builtin_bit_cast(uint32_t, lo) >> 16) | (__builtin_bit_cast(uint32_t, hi) & 0xffff0000u);
+          }
+          *reinterpret_cast<uint4*>(wf + it * 16) = w;
+        } else if constexpr (FB == 16) {
+          *reinterpret_cast<uint4*>(wf + it * 16) = *reinterpret_cast<const uint4*>(src);
+        } else {
+          *reinterpret_cast<uint2*>(wf + it * 8) = *reinterpret_cast<const uint2*>(src);
+        }
       }
       const double* mu = d.mu_snap + (int64_t)b * Bp;
       const float* isc = d.iscale + (int64_t)b * Bp;
@@ -276,8 +351,10 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
           ml = (float)(m - (double)mh);
           is = isc[k];
         }
-        mhs[k] = mh;
-        mls[k] = ml;
+        // the band scale is a power of two, so these products are exact and
+        // fma(v, s, -mh s) - ml s equals ((v - mh) - ml) s bit for bit
+        nqh[k] = -(mh * is);
+        nql[k] = -(ml * is);
         iss[k] = is;                                            // zero past the band count
         oss[k] = k < Bp ? osc[k] : 0.0f;
       }
@@ -285,31 +362,35 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
     __syncthreads();
 
     const uint16_t* xb = static_cast<const uint16_t*>(d.x);
-    uint32_t raw[NS][8];
+    Raw<G> raw[NS][8];
     // Only the last 32-band step can reach past the band count (the earlier
     // steps end at or below 16 (nT - 1) < B); its rows are clamped to B - 1
-    // and zeroed by the band scale.  The earlier steps walk a running row
-    // pointer so no per-load offsets stay live across tiles.
+    // and zeroed by the band scale.
     auto load_raw = [&](int64_t t) {
       const int64_t line = t / tpl;
-      const int smp = W2TP * (int)(t % tpl) + 2 * n;
-      const uint16_t* xl = xb + line * B * Sm + (smp < Sm ? smp : 0);
-      const uint16_t* q = xl + (int64_t)(8 * kg) * Sm;
+      const int smp = TP * (int)(t % tpl) + G * n;
+      // wave-uniform line base + 32-bit byte offsets (a line of B <= 320 rows
+      // is far below 4 GiB): global loads with a scalar base
+      const char* xl = reinterpret_cast<const char*>(xb + line * B * Sm);
+      const uint32_t o = 2u * (uint32_t)(smp < Sm ? smp : 0);
+      const uint32_t lo = o + 2u * (uint32_t)(8 * kg) * (uint32_t)Sm;
+      const uint32_t rs = 2u * (uint32_t)Sm;
+      uint32_t ro = 0;
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
         if (st + 1 < NS) {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            raw[st][j] = *reinterpret_cast<const uint32_t*>(q);
-            q += Sm;
-            asm volatile("" : "+v"(q));
+            raw[st][j].load(xl + (lo + ro));
+            ro += rs;
+            asm volatile("" : "+s"(ro));
           }
-          q += (int64_t)24 * Sm;
+          ro += 24u * rs;
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            const int k = min(32 * st + 8 * kg + j, B - 1);
-            raw[st][j] = *reinterpret_cast<const uint32_t*>(xl + (int64_t)k * Sm);
+            const uint32_t k = (uint32_t)min(32 * st + 8 * kg + j, B - 1);
+            raw[st][j].load(xl + (o + k * rs));
           }
         }
       }
@@ -319,64 +400,75 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
     const int64_t tend = tb0 + nseg;
     for (; t < tend; t += W2W) {
       load_raw(t);
-      const int smp = W2TP * (int)(t % tpl) + 2 * n;
+      const int smp = TP * (int)(t % tpl) + G * n;
       const bool ok = smp < Sm;
-      F xf0[NS], xf1[NS];
+      F xf[G][NS];
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
-        {
-          // re-read per tile: hoisting these tile-invariant values would hold
-          // 24 registers per step for the whole loop
-          int k0 = 32 * st + 8 * kg;
-          asm volatile("" : "+v"(k0));
-          const float4 mh0 = *reinterpret_cast<const float4*>(&mhs[k0]);
-          const float4 mh1 = *reinterpret_cast<const float4*>(&mhs[k0 + 4]);
-          const float4 ml0 = *reinterpret_cast<const float4*>(&mls[k0]);
-          const float4 ml1 = *reinterpret_cast<const float4*>(&mls[k0 + 4]);
-          const float4 is0 = *reinterpret_cast<const float4*>(&iss[k0]);
-          const float4 is1 = *reinterpret_cast<const float4*>(&iss[k0 + 4]);
-          const float mh[8] = {mh0.x, mh0.y, mh0.z, mh0.w, mh1.x, mh1.y, mh1.z, mh1.w};
-          const float ml[8] = {ml0.x, ml0.y, ml0.z, ml0.w, ml1.x, ml1.y, ml1.z, ml1.w};
-          const float is[8] = {is0.x, is0.y, is0.z, is0.w, is1.x, is1.y, is1.z, is1.w};
-          S e0[8], e1[8];
+        // re-read per tile: hoisting these tile-invariant values would hold
+        // 24 registers per step for the whole loop
+        int k0 = 32 * st + 8 * kg;
+        asm volatile("" : "+v"(k0));
+        const float4 qh0 = *reinterpret_cast<const float4*>(&nqh[k0]);
+        const float4 qh1 = *reinterpret_cast<const float4*>(&nqh[k0 + 4]);
+        const float4 ql0 = *reinterpret_cast<const float4*>(&nql[k0]);
+        const float4 ql1 = *reinterpret_cast<const float4*>(&nql[k0 + 4]);
+        const float4 is0 = *reinterpret_cast<const float4*>(&iss[k0]);
+        const float4 is1 = *reinterpret_cast<const float4*>(&iss[k0 + 4]);
+        const float qh[8] = {qh0.x, qh0.y, qh0.z, qh0.w, qh1.x, qh1.y, qh1.z, qh1.w};
+        const float ql[8] = {ql0.x, ql0.y, ql0.z, ql0.w, ql1.x, ql1.y, ql1.z, ql1.w};
+        const float is[8] = {is0.x, is0.y, is0.z, is0.w, is1.x, is1.y, is1.z, is1.w};
+        // samples past the row end are converted too (their loads read
+        // sample 0 of the line); a column never mixes into another column
+        // of the product and their scores are not stored
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float c0 = (((float)(raw[st][j] & 0xffffu) - mh[j]) - ml[j]) * is[j];
-            const float c1 = (((float)(raw[st][j] >> 16) - mh[j]) - ml[j]) * is[j];
-            e0[j] = to_storage<P>(ok ? c0 : 0.0f);
-            e1[j] = to_storage<P>(ok ? c1 : 0.0f);
-          }
-          xf0[st] = pack_frag<P>(e0);
-          xf1[st] = pack_frag<P>(e1);
+        for (int g = 0; g < G; ++g) {
+          float c[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) c[j] = __builtin_fmaf((float)raw[st][j].at(g), is[j], qh[j]) + ql[j];
+          xf[g][st] = cvt_frag<P>(c);
         }
       }
 
-      float dl0 = 0.0f, dl1 = 0.0f;
+      float dl[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) dl[g] = 0.0f;
 #pragma unroll
       for (int i = 0; i < 2 * NS; ++i) {
         if (i < 2 * NS - 1 || i < nT) {
-          typename M::acc a0{}, a1{};
+          typename M::acc a[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) a[g] = typename M::acc{};
 #pragma unroll
           for (int st = 0; st <= i / 2; ++st) {
             const F af = *reinterpret_cast<const F*>(wf + ((fr_off(i) + st) * 64 + lane) * FB);
-            a0 = M::mma(af, xf0[st], a0);
-            a1 = M::mma(af, xf1[st], a1);
-          }
-          const float4 os = *reinterpret_cast<const float4*>(&oss[16 * i + 4 * kg]);
-          const float o4[4] = {os.x, os.y, os.z, os.w};
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float y0 = a0[j] * o4[j], y1 = a1[j] * o4[j];
-            dl0 += y0 * y0;
-            dl1 += y1 * y1;
+            for (int g = 0; g < G; ++g) a[g] = M::mma(af, xf[g][st], a[g]);
+          }
+          if constexpr (P == P_BF16) {                          // row scale already in the operand
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int g = 0; g < G; ++g) dl[g] = __builtin_fmaf(a[g][j], a[g][j], dl[g]);
+          } else {
+            const float4 os = *reinterpret_cast<const float4*>(&oss[16 * i + 4 * kg]);
+            const float o4[4] = {os.x, os.y, os.z, os.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int g = 0; g < G; ++g) {
+                const float y = a[g][j] * o4[j];
+                dl[g] = __builtin_fmaf(y, y, dl[g]);
+              }
           }
         }
       }
-      dl0 += __shfl_xor(dl0, 16, 64);
-      dl0 += __shfl_xor(dl0, 32, 64);
-      dl1 += __shfl_xor(dl1, 16, 64);
-      dl1 += __shfl_xor(dl1, 32, 64);
-      if (kg == 0 && ok) *reinterpret_cast<float2*>(&out[(t / tpl) * Sm + smp]) = float2{dl0, dl1};
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        dl[g] += __shfl_xor(dl[g], 16, 64);
+        dl[g] += __shfl_xor(dl[g], 32, 64);
+      }
+      if (kg == 0 && ok) store_scores<G>(&out[(t / tpl) * Sm + smp], dl);
     }
   }
 }
@@ -524,45 +616,48 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
   using namespace rxk;
   if (wg <= 0) return hipSuccess;
   if (in_type == IN_U16 && (wprec == P_BF16 || wprec == P_F16 || wprec == P_FP8)) {
-    // 16-bit rows with an even sample count and 4-byte aligned base take the
-    // tile kernel (the 16-byte alignment of vec_ok implies both)
-    bool ok = true;
-    for (int i = 0; i < ls->nb; ++i) ok = ok && ls->d[i].vec_ok && (ls->d[i].S % 2 == 0);
+    // 16-bit rows with S % 8 == 0 and 16-byte aligned starts (vec_ok) take
+    // the tile kernel
+    bool ok = Bw % 32 == 0 && Bw >= 32 && Bw <= 32 * MAXS;
+    for (int i = 0; i < ls->nb; ++i) ok = ok && ls->d[i].vec_ok && (ls->d[i].S % 8 == 0);
+    const int ns = Bw / 32;                                  // the launch shares Bw = 32 ceil(nT / 2)
+    const int G = w2_groups(wprec, ns);
+    LaunchSet t = *ls;
+    t.wg0[0] = 0;
+    for (int i = 0; ok && i < ls->nb; ++i) {
+      const BatchDesc& d = ls->d[i];
+      const int64_t tpl = (d.S + 16 * G - 1) / (16 * G);
+      const int64_t tiles = ((int64_t)(d.nblk - 1) * d.blk_lines + d.last_lines) * tpl;
+      if ((int64_t)t.wg0[i] + tiles > INT32_MAX) ok = false;
+      else t.wg0[i + 1] = t.wg0[i] + (int)tiles;
+    }
     if (ok) {
-      LaunchSet t = *ls;
-      t.wg0[0] = 0;
-      for (int i = 0; i < ls->nb; ++i) {
-        const BatchDesc& d = ls->d[i];
-        const int64_t tpl = (d.S + W2TP - 1) / W2TP;
-        const int64_t tiles = ((int64_t)(d.nblk - 1) * d.blk_lines + d.last_lines) * tpl;
-        if ((int64_t)t.wg0[i] + tiles > INT32_MAX) { ok = false; break; }
-        t.wg0[i + 1] = t.wg0[i] + (int)tiles;
+      static int cus[64] = {0};
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+      if (dev < 64 && cus[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipGetLastError();
+        cus[dev] = c;
       }
-      if (ok) {
-        static int cus[64] = {0};
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
-        if (dev < 64 && cus[dev] == 0) {
-          int c = 0;
-          if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return hipGetLastError();
-          cus[dev] = c;
-        }
-        const int ncu = (dev < 64 && cus[dev] > 0) ? cus[dev] : 256;
-        const int64_t ntile = t.wg0[ls->nb];
-        const int g = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, ntile / (2 * W2W)));
-        const int ns = Bw / 32;                                  // the launch shares Bw = 32 ceil(nT / 2)
-        switch (wprec * 16 + ns) {
-#define RXK_W2(PV, N)                                                                                 \
-  case PV * 16 + N: hipLaunchKernelGGL((k_whiten2<PV, N>), dim3(g), dim3(W2NT), 0, st, t, Bw, ntile); break;
-#define RXK_W2P(PV) RXK_W2(PV, 1) RXK_W2(PV, 2) RXK_W2(PV, 3) RXK_W2(PV, 4) RXK_W2(PV, 5) \
-                    RXK_W2(PV, 6) RXK_W2(PV, 7) RXK_W2(PV, 8) RXK_W2(PV, 9) RXK_W2(PV, 10)
-          RXK_W2P(P_BF16) RXK_W2P(P_F16) RXK_W2P(P_FP8)
+      const int ncu = (dev < 64 && cus[dev] > 0) ? cus[dev] : 256;
+      const int64_t ntile = t.wg0[ls->nb];
+      const int g = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, ntile / (2 * W2W)));
+      switch ((wprec * 16 + ns) * 8 + G) {
+#define RXK_W2(PV, N, GG)                                                                              \
+  case (PV * 16 + N) * 8 + GG:                                                                         \
+    hipLaunchKernelGGL((k_whiten2<PV, N, GG>), dim3(g), dim3(W2NT), 0, st, t, Bw, ntile);              \
+    break;
+#define RXK_W2P(PV, GG) RXK_W2(PV, 1, GG) RXK_W2(PV, 2, GG) RXK_W2(PV, 3, GG) RXK_W2(PV, 4, GG) RXK_W2(PV, 5, GG) \
+                        RXK_W2(PV, 6, GG) RXK_W2(PV, 7, GG) RXK_W2(PV, 8, GG) RXK_W2(PV, 9, GG)
+        RXK_W2P(P_BF16, 4) RXK_W2P(P_F16, 4) RXK_W2(P_BF16, 10, 2) RXK_W2(P_F16, 10, 2)
+        RXK_W2(P_FP8, 1, 4) RXK_W2(P_FP8, 2, 4) RXK_W2(P_FP8, 3, 4) RXK_W2(P_FP8, 4, 4) RXK_W2(P_FP8, 5, 4)
+        RXK_W2(P_FP8, 6, 4) RXK_W2(P_FP8, 7, 2) RXK_W2(P_FP8, 8, 2) RXK_W2(P_FP8, 9, 2) RXK_W2(P_FP8, 10, 2)
 #undef RXK_W2P
 #undef RXK_W2
-          default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
+        default: return hipErrorInvalidValue;
       }
+      return hipGetLastError();
     }
   }
 #define RXK_W(INV, PV)                                                                          \
