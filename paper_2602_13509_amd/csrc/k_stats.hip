@@ -348,6 +348,7 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
 // slots in place (centred in FP32, rounded to the operand format) and keeps
 // the exact raw band sums.  Every wave issues the same loads for every chunk,
 // so waiting for a chunk is a fixed count of outstanding loads.
+typedef __attribute__((ext_vector_type(2))) unsigned short u16x2;
 constexpr int S3ROWS = 16 * MAXT;          // rows per ring buffer
 
 // Workgroup barrier that orders LDS accesses only.  A plain __syncthreads()
@@ -385,21 +386,26 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   const uint16_t* xb = static_cast<const uint16_t*>(d.x) + (int64_t)b * d.blk_lines * d.B * d.S;
   const int lrow = lane >> 3, lslot = lane & 7;
 
+  // Round q of a chunk: wave wv loads rows 128 q + 8 wv + lrow, lane slot
+  // lslot holding segment lslot ^ lrow (r & 7 == lrow).  Addresses are a
+  // wave-uniform line base plus a 32-bit per-lane offset; lanes past the band
+  // count or the row end load the line's first word (in bounds) and the
+  // conversion writes zeros over their slot.
+  const int segc = lslot ^ lrow;
+  const uint32_t loff = 2u * ((uint32_t)(8 * wv + lrow) * (uint32_t)d.S + 8u * (uint32_t)segc);
+  const uint32_t qstep = 2u * 128u * (uint32_t)d.S;
   auto issue = [&](int ch, uint16_t* buf) {
     const unsigned line = (unsigned)ch / (unsigned)d.cpl;
     const int s0 = (int)((unsigned)ch - line * (unsigned)d.cpl) * KC;
     const int nvalid = min(KC, d.S - s0);
+    const char* lb = reinterpret_cast<const char*>(xb + (int64_t)line * d.B * d.S + s0);
 #pragma unroll
     for (int q = 0; q < S2IT; ++q) {
       const int r0 = 128 * q + 8 * wv;           // wave-uniform
       if (r0 < d.Bp) {
-        const int r = r0 + lrow;
-        const int seg = lslot ^ (r & 7);
-        const bool ok = (r < d.B) && (8 * seg < nvalid);
-        // lanes past the row end or the band count load a harmless in-bounds
-        // word; the conversion writes zeros over their slot
-        const uint16_t* src = ok ? xb + ((int64_t)line * d.B + r) * d.S + s0 + 8 * seg : xb;
-        __builtin_amdgcn_global_load_lds((const void*)src,
+        const bool ok = (r0 + lrow < d.B) && (8 * segc < nvalid);
+        const uint32_t off = ok ? loff + (uint32_t)q * qstep : 0u;
+        __builtin_amdgcn_global_load_lds((const void*)(lb + off),
                                          (__attribute__((address_space(3))) void*)(buf + r0 * KC), 16, 0, 0);
       }
     }
@@ -414,6 +420,9 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   for (int r = tid; r < d.Bp; r += S2NT) shl[r] = (r < d.B) ? (float)d.shift[(int64_t)b * d.Bp + r] : 0.0f;
   // the direct path runs only when the sample count is a multiple of 8, so an
   // 8-sample segment is either wholly inside the row or wholly past its end
+  // Per 32-bit word (two samples): two converts, two subtractions, one
+  // packed rounding, and the exact raw sum by a 16-bit dot product with
+  // (1, 1); items outside the rows or past the row end become zeros.
   auto convert = [&](int ch, uint16_t* buf) {
     const int s0 = (int)((unsigned)ch % (unsigned)d.cpl) * KC;
     const int nvalid = min(KC, d.S - s0);
@@ -425,16 +434,15 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
       const int seg = slot ^ (r & 7);
       const bool ok = (r < d.B) && (8 * seg < nvalid);
       uint4* p = reinterpret_cast<uint4*>(buf + r * KC + 8 * slot);
-      uint16_t vv[8];
-      unpack8(p, vv);
+      const uint4 wv4 = *p;
+      const uint32_t wd[4] = {ok ? wv4.x : 0u, ok ? wv4.y : 0u, ok ? wv4.z : 0u, ok ? wv4.w : 0u};
       const float sh = shl[r];
       uint32_t o[4];
 #pragma unroll
-      for (int j = 0; j < 8; j += 2) {
-        const S e0 = to_storage<P>(ok ? (float)vv[j] - sh : 0.0f);
-        const S e1 = to_storage<P>(ok ? (float)vv[j + 1] - sh : 0.0f);
-        o[j >> 1] = (uint32_t)e0 | ((uint32_t)e1 << 16);
-        rawsum[q] += ok ? (uint32_t)vv[j] + vv[j + 1] : 0u;
+      for (int h = 0; h < 4; ++h) {
+        const float c0 = (float)(wd[h] & 0xffffu) - sh, c1 = (float)(wd[h] >> 16) - sh;
+        o[h] = ok ? cvt_pack2<P>(c0, c1) : 0u;
+        rawsum[q] = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, wd[h]), u16x2{1, 1}, rawsum[q], false);
       }
       *p = uint4{o[0], o[1], o[2], o[3]};
     }
@@ -533,44 +541,47 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
 }
 
 // ---------------------------------------------------------------------------- merge
-constexpr int MB = 64;      // threads per merge workgroup
+constexpr int MB = 64;      // elements (bands, or matrix entries) per merge workgroup
+constexpr int MW = 4;       // waves per merge workgroup
 constexpr int MAXBLK = 64;  // blocks per batch (reset bits are a 64-bit mask)
 
-// Vector part: one wave per 64 bands.  First every block's exact raw band
-// sum (fixed-order sum over its splits) and shift are gathered (independent
-// loads, all in flight), then the sequential recurrence over blocks: block
-// mean m_b, e = m_b - shift, d = m_b - window mean before the block, window
-// sums after it, and per block the pairwise-update weight N n_b / (N + n_b)
-// (0 when the window was empty: the block's scatter replaces the window's).
-__global__ void __launch_bounds__(MB) k_merge_vec(LaunchSet ls) {
+// Vector part: one workgroup per 64 bands.  The four waves share out the
+// blocks and form every block's exact raw band sum (fixed-order sum over its
+// splits) into LDS, then one wave runs the sequential recurrence over blocks:
+// block mean m_b, e = m_b - shift, d = m_b - window mean before the block,
+// window sums after it, and per block the pairwise-update weight
+// N n_b / (N + n_b) (0 when the window was empty: the block's scatter
+// replaces the window's).
+__global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
   int local;
   const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
   __shared__ double sb[MAXBLK][MB];
   __shared__ double shb[MAXBLK][MB];
-  const int k = MB * local + threadIdx.x;
+  const int lane = threadIdx.x & (MB - 1), w = threadIdx.x / MB;
+  const int k = MB * local + lane;
   const bool in = k < d.B;
-#pragma unroll 4
-  for (int b = 0; b < d.nblk; ++b) {
+  for (int b = w; b < d.nblk; b += MW) {
     const int ksb = ks_of(d, b);
     double t = 0.0;
     if (in)
       for (int s = 0; s < ksb; ++s) t += d.psum[((int64_t)b * d.ks + s) * d.Bp + k];
-    sb[b][threadIdx.x] = t;
-    shb[b][threadIdx.x] = (k < d.Bp) ? d.shift[(int64_t)b * d.Bp + k] : 0.0;
+    sb[b][lane] = t;
+    shb[b][lane] = (k < d.Bp) ? d.shift[(int64_t)b * d.Bp + k] : 0.0;
   }
-  if (k >= d.Bp) return;
+  __syncthreads();
+  if (w != 0 || k >= d.Bp) return;
   double N = (double)d.n_in;
   double s1 = in ? d.s1_in[k] : 0.0;
   for (int b = 0; b < d.nblk; ++b) {
     const double nb = (double)blk_lines_of(d, b) * d.S;
     if ((d.reset_bits >> b) & 1ull) { N = 0.0; s1 = 0.0; }
-    const double mb = sb[b][threadIdx.x] / nb;
+    const double mb = sb[b][lane] / nb;
     const int64_t o = (int64_t)b * d.Bp + k;
-    d.ev[o] = in ? mb - shb[b][threadIdx.x] : 0.0;
+    d.ev[o] = in ? mb - shb[b][lane] : 0.0;
     d.dv[o] = (in && N > 0.0) ? mb - s1 / N : 0.0;
     if (k == 0) d.coef[b] = N > 0.0 ? N * nb / (N + nb) : 0.0;
-    s1 += sb[b][threadIdx.x];
+    s1 += sb[b][lane];
     N += nb;
     d.mu_snap[o] = in ? s1 / N : 0.0;
     if (k == 0) d.n_snap[b] = N;
@@ -578,36 +589,45 @@ __global__ void __launch_bounds__(MB) k_merge_vec(LaunchSet ls) {
   d.s1_out[k] = in ? s1 : 0.0;
 }
 
-// Matrix part: one wave per quarter of a lower 16x16 tile (4 rows x 16
-// columns), one element per lane: C_b = fixed-order FP64 sum of the split
-// partials, M2_b = C_b - n_b e e^T (exact shift correction), then the
-// pairwise update M2 <- M2 + M2_b + w d d^T (or M2 <- M2_b for an empty
-// window), the window's scatter matrix snapshotted after every block.
+// Matrix part: one workgroup per quarter of a lower 16x16 tile (4 rows x 16
+// columns, one entry per lane).  The four waves share out the blocks:
+// C_b = fixed-order FP64 sum of the split partials, M2_b = C_b - n_b e e^T
+// (exact shift correction), into LDS; then one wave runs the pairwise
+// update M2 <- M2 + M2_b + w d d^T (or M2 <- M2_b for an empty window),
+// snapshotting the window's scatter matrix after every block.
 template <typename PT>
-__global__ void __launch_bounds__(MB) k_merge_mat(LaunchSet ls) {
+__global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
   int q;
   const int bi = find_batch(ls, blockIdx.x, q);
   const BatchDesc& d = ls.d[bi];
+  __shared__ double mbl[MAXBLK][MB];
+  const int lane = threadIdx.x & (MB - 1), w = threadIdx.x / MB;
   const int t = q >> 2;
   int ti = 0;
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
   const int tj = t - ti * (ti + 1) / 2;
-  const int gi = 16 * ti + 4 * (q & 3) + (threadIdx.x >> 4), gj = 16 * tj + (threadIdx.x & 15);
-  if (!(gi < d.B && gj < d.B && gi >= gj)) return;
+  const int gi = 16 * ti + 4 * (q & 3) + (lane >> 4), gj = 16 * tj + (lane & 15);
+  const bool live = gi < d.B && gj < d.B && gi >= gj;
   const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
+  if (live) {
+    for (int b = w; b < d.nblk; b += MW) {
+      const double nb = (double)blk_lines_of(d, b) * d.S;
+      const int ksb = ks_of(d, b);
+      const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
+      double c = 0.0;
+      for (int s = 0; s < ksb; ++s) c += (double)pb[s * bp2];
+      const int64_t o = (int64_t)b * d.Bp;
+      mbl[b][lane] = c - nb * d.ev[o + gi] * d.ev[o + gj];
+    }
+  }
+  __syncthreads();
+  if (w != 0 || !live) return;
   double m2 = d.m2_in[e];
-#pragma unroll 4
   for (int b = 0; b < d.nblk; ++b) {
-    const double nb = (double)blk_lines_of(d, b) * d.S;
-    const int ksb = ks_of(d, b);
     if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
-    const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
-    double c = 0.0;
-    for (int s = 0; s < ksb; ++s) c += (double)pb[s * bp2];
     const int64_t o = (int64_t)b * d.Bp;
-    const double m2b = c - nb * d.ev[o + gi] * d.ev[o + gj];
-    const double w = d.coef[b];
-    m2 = (w > 0.0) ? m2 + m2b + w * d.dv[o + gi] * d.dv[o + gj] : m2b;
+    const double wgt = d.coef[b];
+    m2 = (wgt > 0.0) ? m2 + mbl[b][lane] + wgt * d.dv[o + gi] * d.dv[o + gj] : mbl[b][lane];
     d.m2_snap[b * bp2 + e] = m2;
   }
   d.m2_out[e] = m2;
@@ -622,10 +642,10 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const r
                                        const rxk::LaunchSet* ls2, int wg2, hipStream_t st) {
   using namespace rxk;
   if (phase == 2) {
-    if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(MB), 0, st, *ls);
+    if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(MB * MW), 0, st, *ls);
     if (wg2 > 0) {
-      if (prec == P_F64) hipLaunchKernelGGL((k_merge_mat<double>), dim3(wg2), dim3(MB), 0, st, *ls2);
-      else hipLaunchKernelGGL((k_merge_mat<float>), dim3(wg2), dim3(MB), 0, st, *ls2);
+      if (prec == P_F64) hipLaunchKernelGGL((k_merge_mat<double>), dim3(wg2), dim3(MB * MW), 0, st, *ls2);
+      else hipLaunchKernelGGL((k_merge_mat<float>), dim3(wg2), dim3(MB * MW), 0, st, *ls2);
     }
     return hipGetLastError();
   }

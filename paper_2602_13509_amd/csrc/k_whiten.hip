@@ -207,18 +207,6 @@ template <> __device__ __forceinline__ long pack_frag<P_FP8>(const uint8_t e[8])
   return __builtin_bit_cast(long, w);
 }
 
-// Round two FP32 values to the operand format (RNE) and pack them, low
-// value first.  BF16 and FP16 convert both in one instruction.
-typedef __attribute__((ext_vector_type(2))) float f32x2;
-typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
-typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
-template <int P> __device__ __forceinline__ uint32_t cvt_pack2(float a, float b);
-template <> __device__ __forceinline__ uint32_t cvt_pack2<P_BF16>(float a, float b) {
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
-}
-template <> __device__ __forceinline__ uint32_t cvt_pack2<P_F16>(float a, float b) {
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
-}
 // Eight centred values -> one operand fragment.
 template <int P> __device__ __forceinline__ typename MM<P>::frag cvt_frag(const float c[8]) {
   if constexpr (P == P_FP8) {

@@ -116,6 +116,18 @@ template <> __device__ __forceinline__ uint16_t to_storage<P_BF16>(float v) { re
 template <> __device__ __forceinline__ uint16_t to_storage<P_F16>(float v) { return f32_to_f16_bits(v); }
 template <> __device__ __forceinline__ uint8_t to_storage<P_FP8>(float v) { return f32_to_e4m3(v); }
 
+// Round two FP32 values to the operand format (RNE) and pack them, low
+// value first.  BF16 and FP16 convert both in one instruction.
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
+template <int P> __device__ __forceinline__ uint32_t cvt_pack2(float a, float b);
+template <> __device__ __forceinline__ uint32_t cvt_pack2<P_BF16>(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+template <> __device__ __forceinline__ uint32_t cvt_pack2<P_F16>(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, f16x2));
+}
 // Load one operand fragment: KV consecutive storage elements at p.
 template <int P> __device__ __forceinline__ typename MM<P>::frag load_frag(const typename MM<P>::storage* p);
 template <> __device__ __forceinline__ double load_frag<P_F64>(const double* p) { return *p; }

@@ -86,7 +86,10 @@ static void dev_free(DevBuf& b) {
 // ---------------------------------------------------------------------------- geometry
 static constexpr uint32_t kMagic = 0x52585354u;   // "RXST"
 static constexpr int kSplitChunks = 64;            // pixel chunks per covariance split, 64x64 super-tile kernel
-static constexpr int kSplitChunks2 = 80;           // pixel chunks per covariance split, whole-triangle kernel
+// Pixel chunks per covariance split, whole-triangle kernel (one workgroup per
+// CU): 84 makes a 100-line block of 640 samples 12 splits, so 20 such blocks
+// pushed together fill one pass of 256 CUs (240 workgroups, not 260).
+static constexpr int kSplitChunks2 = 84;
 static constexpr int kMaxBlocksPerBatch = 64;      // reset bits are a 64-bit mask
 
 static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
