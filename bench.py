@@ -103,6 +103,64 @@ def latency(rx, torch, x, prec, nblocks):
     return float(np.median(lat)), float(np.quantile(lat, 0.99))
 
 
+def serving(rx, torch, seconds, replay_all_at_once):
+    """Served form: 16 streams over every (S, B) in {320, 640, 1024} x {120,
+    200, 270, 300} plus seeded repeats, Poisson block arrivals of 16-128 lines
+    at 100-400 lines/s per stream, cumulative windows, BF16 path.  Each stream
+    cycles blocks out of one resident 128-line sensor cube (the content does
+    not change the work).  Blocks are submitted at their arrival times (or all
+    at once) and the server is stepped continuously: whatever is queued joins
+    the next batched launch while earlier launches are still running.
+    Latency = arrival -> completion seen by a non-blocking poll."""
+    from paper_2602_13509_amd import synth
+    specs = synth.served_streams(0, n_streams=16, duration_s=seconds)
+    srv = rx.RxServer(64 << 30, 16)
+    streams, cubes = [], []
+    for sp in specs:
+        c = synth.sensor_cube(sp.seed, lines=128, samples=sp.samples, bands=sp.bands, chunk_lines=64).cube
+        cubes.append(torch.from_numpy(c).cuda())
+        cfg = rx.make_config(sp.bands, sp.samples, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=RIDGE,
+                             block_lines=128)
+        streams.append(rx.RxStream(cfg, server=srv))
+    ev = sorted((0.0 if replay_all_at_once else float(t), i, int(n))
+                for i, sp in enumerate(specs) for t, n in zip(sp.arrivals, sp.block_lines))
+    arrive, px_of, owner = {}, {}, {}
+    outs = [torch.empty(128 * sp.samples, dtype=torch.float32, device="cuda") for sp in specs]
+    lat, total_px = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k, tag, launched = 0, 0, 0
+    while len(lat) < len(ev):
+        now = time.perf_counter() - t0
+        while k < len(ev) and ev[k][0] <= now:
+            t_arr, i, n = ev[k]
+            srv.rx_server_submit(streams[i], cubes[i][:n], tag)
+            arrive[tag] = t_arr
+            px_of[tag] = n * specs[i].samples
+            owner[tag] = i
+            tag += 1
+            k += 1
+        launched += srv.rx_server_step()
+        for d in srv.rx_server_poll(block=False):
+            lat.append(time.perf_counter() - t0 - arrive[d])
+            total_px += px_of[d]
+            streams[owner[d]].rx_scores(outs[owner[d]])    # pop the block's scores (device to device)
+        if now > seconds + 120.0:
+            raise RuntimeError(f"served run did not drain: {len(lat)} of {len(ev)} blocks done")
+    t_end = time.perf_counter() - t0
+    for st in streams:
+        st.scores_host()                      # drain the FIFOs (not timed)
+        st.rx_destroy()
+    srv.rx_server_destroy()
+    lat = np.array(lat) * 1e3
+    offered = sum(int(np.sum(sp.block_lines)) * sp.samples for sp in specs) / seconds
+    return {"streams": len(specs), "blocks": len(ev), "arrival_window_s": seconds,
+            "all_at_once": replay_all_at_once, "px": int(total_px), "wall_s": t_end,
+            "px_per_s": total_px / t_end, "offered_px_per_s": offered,
+            "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99)),
+                           "max": float(lat.max())}}
+
+
 def cpu_baseline(cube, budget_s):
     """The FP64 oracle as it stands, on the first blocks of the same cube, for
     about budget_s seconds of CPU time (at least one block)."""
@@ -132,6 +190,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="arrival window of the served-streams run (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build's path runs on a single MI355X "
@@ -153,6 +213,16 @@ def main():
     t_64, ms_64, n_64, sc_64 = run_path(rx, torch, x, "fp64", k64, 1, "fp64")
     p50, p99 = latency(rx, torch, x, "bf16", 40)
     log(f"block latency (100 lines): p50 {p50:.3f} ms, p99 {p99:.3f} ms")
+
+    served = None
+    if args.serve_seconds > 0:
+        nominal = serving(rx, torch, args.serve_seconds, False)
+        log(f"served (16 streams, nominal arrivals): {nominal['px_per_s']:.3e} px/s, block latency p50 "
+            f"{nominal['latency_ms']['p50']:.3f} ms, p99 {nominal['latency_ms']['p99']:.3f} ms")
+        saturated = serving(rx, torch, args.serve_seconds, True)
+        log(f"served (16 streams, all blocks at once): {saturated['px_per_s']:.3e} px/s, p99 "
+            f"{saturated['latency_ms']['p99']:.3f} ms")
+        served = {"nominal": nominal, "saturated": saturated}
 
     cpu, ref = cpu_baseline(cube, args.cpu_seconds)
     nref = ref.size
@@ -194,6 +264,7 @@ def main():
         "latency_ms": {"block_lines": BLOCK, "p50": p50, "p99": p99},
         "score_error_vs_oracle": {"max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
                                   "pixels": int(nref)},
+        "serving": served,
         "roofline": roof,
         "phases": phases,
         "cpu_baseline": cpu,

@@ -651,13 +651,27 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const r
   }
   if (wg <= 0) return hipSuccess;
   if (phase == 1 && in_type == IN_U16 && (prec == P_BF16 || prec == P_F16)) {
-    bool aligned = true;
-    for (int i = 0; i < ls->nb; ++i) aligned = aligned && ls->d[i].vec_ok;
-    if (aligned) {
-      if (prec == P_BF16) hipLaunchKernelGGL((k_syrk3<P_BF16>), dim3(wg), dim3(S2NT), 0, st, *ls);
-      else hipLaunchKernelGGL((k_syrk3<P_F16>), dim3(wg), dim3(S2NT), 0, st, *ls);
-      return hipGetLastError();
+    // aligned 16-bit batches take the direct-load kernel, the others the
+    // register-staged one; the choice is per batch, so a block's partials
+    // never depend on what else shares the launch
+    LaunchSet a, o;
+    a.nb = o.nb = 0;
+    a.wg0[0] = o.wg0[0] = 0;
+    for (int i = 0; i < ls->nb; ++i) {
+      LaunchSet& t = ls->d[i].vec_ok ? a : o;
+      t.d[t.nb] = ls->d[i];
+      t.wg0[t.nb + 1] = t.wg0[t.nb] + (ls->wg0[i + 1] - ls->wg0[i]);
+      ++t.nb;
     }
+    if (a.nb > 0) {
+      if (prec == P_BF16) hipLaunchKernelGGL((k_syrk3<P_BF16>), dim3(a.wg0[a.nb]), dim3(S2NT), 0, st, a);
+      else hipLaunchKernelGGL((k_syrk3<P_F16>), dim3(a.wg0[a.nb]), dim3(S2NT), 0, st, a);
+    }
+    if (o.nb > 0) {
+      if (prec == P_BF16) hipLaunchKernelGGL((k_syrk2<IN_U16, P_BF16>), dim3(o.wg0[o.nb]), dim3(S2NT), 0, st, o);
+      else hipLaunchKernelGGL((k_syrk2<IN_U16, P_F16>), dim3(o.wg0[o.nb]), dim3(S2NT), 0, st, o);
+    }
+    return hipGetLastError();
   }
 #define RXK_CASE(INV, PV)                                                                      \
   if (in_type == INV && prec == PV) {                                                          \

@@ -603,23 +603,31 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
                                         hipStream_t st) {
   using namespace rxk;
   if (wg <= 0) return hipSuccess;
-  if (in_type == IN_U16 && (wprec == P_BF16 || wprec == P_F16 || wprec == P_FP8)) {
-    // 16-bit rows with S % 8 == 0 and 16-byte aligned starts (vec_ok) take
-    // the tile kernel
-    bool ok = Bw % 32 == 0 && Bw >= 32 && Bw <= 32 * MAXS;
-    for (int i = 0; i < ls->nb; ++i) ok = ok && ls->d[i].vec_ok && (ls->d[i].S % 8 == 0);
+  if (in_type == IN_U16 && (wprec == P_BF16 || wprec == P_F16 || wprec == P_FP8) && Bw % 32 == 0 && Bw >= 32 &&
+      Bw <= 32 * MAXS) {
+    // batches of 16-bit rows with S % 8 == 0 and 16-byte aligned starts
+    // (vec_ok) take the tile kernel, the others the chunk kernel; the choice
+    // is per batch (both give the same scores, bit for bit)
     const int ns = Bw / 32;                                  // the launch shares Bw = 32 ceil(nT / 2)
     const int G = w2_groups(wprec, ns);
-    LaunchSet t = *ls;
-    t.wg0[0] = 0;
-    for (int i = 0; ok && i < ls->nb; ++i) {
+    LaunchSet t, o;
+    t.nb = o.nb = 0;
+    t.wg0[0] = o.wg0[0] = 0;
+    for (int i = 0; i < ls->nb; ++i) {
       const BatchDesc& d = ls->d[i];
       const int64_t tpl = (d.S + 16 * G - 1) / (16 * G);
       const int64_t tiles = ((int64_t)(d.nblk - 1) * d.blk_lines + d.last_lines) * tpl;
-      if ((int64_t)t.wg0[i] + tiles > INT32_MAX) ok = false;
-      else t.wg0[i + 1] = t.wg0[i] + (int)tiles;
+      if (d.vec_ok && d.S % 8 == 0 && (int64_t)t.wg0[t.nb] + tiles <= INT32_MAX) {
+        t.d[t.nb] = d;
+        t.wg0[t.nb + 1] = t.wg0[t.nb] + (int)tiles;
+        ++t.nb;
+      } else {
+        o.d[o.nb] = d;
+        o.wg0[o.nb + 1] = o.wg0[o.nb] + (ls->wg0[i + 1] - ls->wg0[i]);
+        ++o.nb;
+      }
     }
-    if (ok) {
+    if (t.nb > 0) {
       static int cus[64] = {0};
       int dev = 0;
       if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
@@ -629,7 +637,7 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
         cus[dev] = c;
       }
       const int ncu = (dev < 64 && cus[dev] > 0) ? cus[dev] : 256;
-      const int64_t ntile = t.wg0[ls->nb];
+      const int64_t ntile = t.wg0[t.nb];
       const int g = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, ntile / (2 * W2W)));
       switch ((wprec * 16 + ns) * 8 + G) {
 #define RXK_W2(PV, N, GG)                                                                              \
@@ -645,8 +653,12 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
 #undef RXK_W2
         default: return hipErrorInvalidValue;
       }
-      return hipGetLastError();
     }
+    if (o.nb == 0) return hipGetLastError();
+    if (wprec == P_BF16) hipLaunchKernelGGL((k_whiten<IN_U16, P_BF16>), dim3(o.wg0[o.nb]), dim3(NT), 0, st, o, Bw);
+    else if (wprec == P_F16) hipLaunchKernelGGL((k_whiten<IN_U16, P_F16>), dim3(o.wg0[o.nb]), dim3(NT), 0, st, o, Bw);
+    else hipLaunchKernelGGL((k_whiten<IN_U16, P_FP8>), dim3(o.wg0[o.nb]), dim3(NT), 0, st, o, Bw);
+    return hipGetLastError();
   }
 #define RXK_W(INV, PV)                                                                          \
   if (in_type == INV && wprec == PV) {                                                          \

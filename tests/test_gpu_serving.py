@@ -1,0 +1,152 @@
+"""Serving through the C ABI: many streams of different widths and band
+counts admitted on one server, their blocks batched into shared launches.
+
+The property under test: a stream's scores are the same alone and in any
+mix, bit for bit (every reduction of the path is fixed per block, never by
+what shares the launch), and they match the FP64 oracle within the BF16
+tolerance of the scoring tests."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_scores, oracle_stream_scores, say
+from paper_2602_13509_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16 = (5e-2, 1e-2)
+
+
+@pytest.fixture(scope="module")
+def rxm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_13509_amd import rx
+    return rx
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_streams(seed):
+    """(B, S, block sizes, cube) per stream; S = 204 rows are not 16-byte
+    multiples, so that stream takes the register-staged kernels while the
+    others take the direct-load and tile kernels in the same launches."""
+    rng = np.random.default_rng(seed)
+    shapes = [(120, 320), (200, 640), (270, 640), (300, 1024), (270, 320), (200, 204)]
+    out = []
+    for i, (B, S) in enumerate(shapes):
+        blocks = [int(v) for v in rng.integers(16, 49, size=3)]
+        cube = synth.sensor_cube(100 + i, lines=sum(blocks), samples=S, bands=B).cube
+        out.append((B, S, blocks, cube))
+    return out
+
+
+def cfg_for(rxm, B, S, block_lines):
+    return rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                           block_lines=block_lines)
+
+
+def test_served_mix_equals_alone_bitwise(rxm):
+    import torch
+    streams = make_streams(7)
+    dcubes = [dev(c) for (_, _, _, c) in streams]
+
+    # alone: one stream at a time, one push per block
+    alone = []
+    for (B, S, blocks, cube), dc in zip(streams, dcubes):
+        st = rxm.RxStream(cfg_for(rxm, B, S, 0))
+        l0 = 0
+        for n in blocks:
+            st.rx_push_lines(dc[l0:l0 + n])
+            l0 += n
+        st.rx_sync()
+        alone.append(st.scores_host())
+        st.rx_destroy()
+
+    # mixed: every stream admitted on one server, blocks submitted in an
+    # interleaved random order, stepped until drained
+    srv = rxm.RxServer(8 << 30, 16)
+    served = [rxm.RxStream(cfg_for(rxm, B, S, 64), server=srv) for (B, S, _, _) in streams]
+    order = [(i, j) for i, s in enumerate(streams) for j in range(len(s[2]))]
+    rng = np.random.default_rng(3)
+    rng.shuffle(order)
+    nxt = [0] * len(streams)
+    starts = [np.concatenate([[0], np.cumsum(s[2])]) for s in streams]
+    tag = 0
+    for i, _ in order:                      # a stream's blocks keep their own order
+        j = nxt[i]
+        nxt[i] += 1
+        l0, l1 = int(starts[i][j]), int(starts[i][j + 1])
+        srv.rx_server_submit(served[i], dcubes[i][l0:l1], tag)
+        tag += 1
+    steps, done = 0, []
+    while True:
+        q, _, _ = srv.rx_server_queued()
+        if q == 0:
+            break
+        n = srv.rx_server_step()
+        steps += 1
+        assert n >= 1
+    done = srv.rx_server_poll(block=True)
+    assert sorted(done) == list(range(tag))
+    say(f"served mix: {len(streams)} streams, {tag} blocks in {steps} steps")
+    torch.cuda.synchronize()
+    for k, ((B, S, blocks, cube), st) in enumerate(zip(streams, served)):
+        got = st.scores_host()
+        assert got.shape == alone[k].shape
+        assert np.array_equal(got.view(np.uint32), alone[k].view(np.uint32)), f"stream {k} (B={B}, S={S})"
+        ref, _ = oracle_stream_scores(cube, B, S, pushes=blocks, rho=1e-6)
+        assert_scores(got, ref, B, *TOL_BF16, label=f"served B={B} S={S}")
+        st.rx_destroy()
+    srv.rx_server_destroy()
+
+
+def test_server_admission_by_budget_and_slots(rxm):
+    cfg = cfg_for(rxm, 270, 640, 64)
+    need = rxm.stream_footprint(cfg, 64)
+    srv = rxm.RxServer(int(2.5 * need), 8)
+    a = rxm.RxStream(cfg, server=srv)
+    b = rxm.RxStream(cfg, server=srv)
+    with pytest.raises(rxm.RxError) as e:
+        rxm.RxStream(cfg, server=srv)
+    assert e.value.status == rxm.RX_E_BUDGET
+    _, _, used = srv.rx_server_queued()
+    assert used == 2 * need
+    a.rx_destroy()                          # frees its admission
+    c = rxm.RxStream(cfg, server=srv)
+    b.rx_destroy()
+    c.rx_destroy()
+    srv.rx_server_destroy()
+
+    slots = rxm.RxServer(64 * need, 1)
+    x = rxm.RxStream(cfg, server=slots)
+    with pytest.raises(rxm.RxError) as e:
+        rxm.RxStream(cfg, server=slots)
+    assert e.value.status == rxm.RX_E_BUDGET
+    x.rx_destroy()
+    slots.rx_server_destroy()
+
+
+def test_server_tags_in_launch_order_and_block_limit(rxm):
+    B, S = 64, 128
+    cube = synth.sensor_cube(31, lines=60, samples=S, bands=B).cube
+    dc = dev(cube)
+    srv = rxm.RxServer(1 << 30, 4)
+    st = rxm.RxStream(cfg_for(rxm, B, S, 20), server=srv)
+    with pytest.raises(rxm.RxError) as e:
+        srv.rx_server_submit(st, dc[0:21], 99)           # longer than the stream's block limit
+    assert e.value.status == rxm.RX_E_ARG
+    for t in range(3):
+        srv.rx_server_submit(st, dc[20 * t:20 * (t + 1)], 10 + t)
+    assert srv.rx_server_step() == 1                     # one block per stream per step
+    assert srv.rx_server_step() == 1
+    assert srv.rx_server_step() == 1
+    assert srv.rx_server_step() == 0
+    assert srv.rx_server_poll(block=True) == [10, 11, 12]
+    got = st.scores_host()
+    ref, _ = oracle_stream_scores(cube, B, S, pushes=[20, 20, 20], rho=1e-6)
+    assert_scores(got, ref, B, *TOL_BF16, label="served single stream")
+    st.rx_destroy()
+    srv.rx_server_destroy()
