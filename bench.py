@@ -39,12 +39,63 @@ def log(msg):
 
 
 def phase_work(B, px, esz, nblk):
-    """Algorithmic flops and HBM bytes per launch of each phase."""
+    """Algorithmic work per launch of each phase (one launch covers the push's
+    nblk blocks): (bound, flops, HBM bytes, flop peak key).
+      covariance    B(B+1) flop and B esz bytes per pixel (lower triangle)
+      whiten_score  B(B+1) + 2B flop, B esz + 4 bytes per pixel
+      factor        2 B^3 / 3 FP64 flop per block (Cholesky B^3/3 + triangular
+                    inverse B^3/3), B^2 8 bytes read and B^2 8 + B^2 2 written
+      merge         per block: the split partials of the lower triangle (FP32)
+                    read, the FP64 window snapshot written"""
+    ks = -(-BLOCK * (-(-SAMPLES // 64)) // 84)
+    tri = B * (B + 1) // 2
     return {
-        "covariance": (px * B * (B + 1), px * B * esz),
-        "whiten_score": (px * (B * (B + 1) + 2 * B), px * (B * esz + 4)),
-        "factor": (nblk * (2 * B ** 3 / 3.0), nblk * B * B * 8 * 2),
+        "covariance": ("hbm", px * B * (B + 1), px * B * esz, "bf16"),
+        "whiten_score": ("hbm", px * (B * (B + 1) + 2 * B), px * (B * esz + 4), "bf16"),
+        "factor": ("mfma", nblk * 2.0 * B ** 3 / 3.0, nblk * B * B * (8 + 8 + 2), "fp64"),
+        "merge": ("hbm", nblk * 2.0 * tri * ks, nblk * (tri * ks * 4 + tri * 8), "fp64"),
     }
+
+
+def roofline(kernel, w, ms):
+    bound, fl, by, pk = w
+    sec = ms * 1e-3
+    if bound == "hbm":
+        r = {"kernel": kernel, "bound": "hbm", "achieved": by / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": by / sec / 1e9 / HBM_PEAK_GBS, "mfma_frac": fl / sec / 1e12 / PEAK_TFLOPS[pk]}
+    else:
+        r = {"kernel": kernel, "bound": "mfma", "achieved": fl / sec / 1e12, "peak": PEAK_TFLOPS[pk],
+             "unit": "TFLOP/s", "frac": fl / sec / 1e12 / PEAK_TFLOPS[pk], "dtype": pk}
+    r.update({"algorithmic_flops": fl, "algorithmic_bytes": by, "avg_launch_ms": ms})
+    return r
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_sensor_2000x640x270.md")
+KERNEL_SOURCES = {"covariance": "k_stats.hip", "merge": "k_stats.hip", "factor": "k_factor.hip",
+                  "whiten_score": "k_whiten.hip"}
+
+
+def measured_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size), or None when there is none or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1)).get(phase)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_2602_13509_amd", "csrc", KERNEL_SOURCES[phase])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def run_path(rx, torch, x, prec, steps, warmup, label):
@@ -192,6 +243,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="arrival window of the served-streams run (0 skips it)")
+    ap.add_argument("--skip-fp64", action="store_true", help="skip the plain FP64 path (short profiling runs)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="end with one device-to-device copy of this many MiB: the reference kernel that "
+                         "scales hardware byte counters under rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build's path runs on a single MI355X "
@@ -210,7 +265,10 @@ def main():
 
     t_mix, ms_mix, n_mix, sc_mix = run_path(rx, torch, x, "bf16", args.steps, args.warmup, "mixed bf16")
     k64 = max(2, args.steps // 5)
-    t_64, ms_64, n_64, sc_64 = run_path(rx, torch, x, "fp64", k64, 1, "fp64")
+    if args.skip_fp64:
+        t_64, ms_64, n_64 = float("nan"), [0.0] * 5, [0] * 5
+    else:
+        t_64, ms_64, n_64, _ = run_path(rx, torch, x, "fp64", k64, 1, "fp64")
     p50, p99 = latency(rx, torch, x, "bf16", 40)
     log(f"block latency (100 lines): p50 {p50:.3f} ms, p99 {p99:.3f} ms")
 
@@ -224,31 +282,36 @@ def main():
             f"{saturated['latency_ms']['p99']:.3f} ms")
         served = {"nominal": nominal, "saturated": saturated}
 
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"reference copy: {args.copy_mib} MiB device to device")
+        del src, dst
+
     cpu, ref = cpu_baseline(cube, args.cpu_seconds)
     nref = ref.size
     err = np.abs(sc_mix[:nref] - ref) / np.maximum(ref, 1e-3 * BANDS)
     log(f"cpu oracle {cpu['value']:.3e} px/s on {cpu['cores']} threads; mixed vs oracle (same ridge): "
         f"max rel {err.max():.3e}, p99 rel {np.quantile(err, 0.99):.3e}")
 
-    # roofline of the dominant kernel of the mixed path (live HIP-event timing)
+    # roofline of the dominant kernel of the mixed path: the phase with the
+    # longest launch, timed live with HIP events on the library's stream
     work = phase_work(BANDS, npx, 2, LINES // BLOCK)
     per = {PHASES[i]: ms_mix[i] / max(n_mix[i], 1) for i in range(5)}
-    dom = max(("covariance", "whiten_score"), key=lambda p: per[p])
-    fl, by = work[dom]
-    sec = per[dom] * 1e-3
-    roof = {"kernel": dom, "bound": "hbm", "achieved": by / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": by / sec / 1e9 / HBM_PEAK_GBS, "traffic": None,
-            "mfma_frac": fl / sec / 1e12 / PEAK_TFLOPS["bf16"],
-            "algorithmic_bytes": by, "algorithmic_flops": fl, "avg_launch_ms": per[dom]}
+    dom = max(work, key=lambda p: per[p])
+    roof = roofline(dom, work[dom], per[dom])
+    roof["traffic"] = measured_traffic(dom)
     phases = {}
     for i, p in enumerate(PHASES):
-        phases[p] = {"mixed_ms": per[p], "fp64_ms": ms_64[i] / max(n_64[i], 1)}
-        if p in work:
-            f_, b_ = work[p]
-            phases[p]["mixed_tflops"] = f_ / (per[p] * 1e-3) / 1e12 if per[p] > 0 else None
-            phases[p]["mixed_gbs"] = b_ / (per[p] * 1e-3) / 1e9 if per[p] > 0 else None
-            t64 = ms_64[i] / max(n_64[i], 1)
-            phases[p]["fp64_tflops"] = f_ / (t64 * 1e-3) / 1e12 if t64 > 0 else None
+        phases[p] = {"mixed_ms": per[p], "fp64_ms": (ms_64[i] / n_64[i]) if n_64[i] else None}
+        if p in work and per[p] > 0:
+            r = roofline(p, work[p], per[p])
+            phases[p].update({"bound": r["bound"], "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]})
+            if r["bound"] == "hbm":
+                phases[p]["mfma_frac"] = r["mfma_frac"]
 
     value = npx / t_mix
     rec = {
@@ -259,8 +322,8 @@ def main():
         "config": {"workload": "sensor cube 2000 lines x 640 samples x 270 bands uint16, 20 blocks of 100 "
                                "lines, update-then-score, BF16 covariance + whitening, FP64 factor, ridge 1e-6",
                    "lines": LINES, "samples": SAMPLES, "bands": BANDS, "block_lines": BLOCK},
-        "fp64_path": {"value": npx / t_64, "ms_per_step": t_64 * 1e3, "steps": k64},
-        "mixed_over_fp64": t_64 / t_mix,
+        "fp64_path": None if args.skip_fp64 else {"value": npx / t_64, "ms_per_step": t_64 * 1e3, "steps": k64},
+        "mixed_over_fp64": None if args.skip_fp64 else t_64 / t_mix,
         "latency_ms": {"block_lines": BLOCK, "p50": p50, "p99": p99},
         "score_error_vs_oracle": {"max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
                                   "pixels": int(nref)},

@@ -32,7 +32,7 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 }
 
 template <int WP, int FTPW>
-__global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
+__global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
   int b;
   const int bi = find_batch(ls, blockIdx.x, b);
   const BatchDesc& d = ls.d[bi];
@@ -266,6 +266,7 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
   }
   if constexpr (WP != P_F64) {
     using S = typename MM<WP>::storage;
+    const int Bw = 32 * ((Bp + 31) / 32);           // operand row pitch of this batch
     S* wl = static_cast<S*>(d.wlp) + (int64_t)b * Bp * Bw;
     __syncthreads();
     if constexpr (LP) {           // row maxima of |W_ij 2^e_j|: one wave per row, lanes over columns
@@ -296,26 +297,26 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls, int Bw) {
 }  // namespace rxk
 
 template <int WP>
-static void launch_factor_t(const rxk::LaunchSet* ls, int wg, int Bw, hipStream_t st) {
+static void launch_factor_t(const rxk::LaunchSet* ls, int wg, hipStream_t st) {
   using namespace rxk;
   int T = 0;                                // the largest band-tile count of the launch sizes the tile array
   for (int i = 0; i < ls->nb; ++i) T = T > ls->d[i].Bp / 16 ? T : ls->d[i].Bp / 16;
-  if (T <= 12) hipLaunchKernelGGL((k_factor<WP, ftpw_for(12)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
-  else if (T <= 17) hipLaunchKernelGGL((k_factor<WP, ftpw_for(17)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
-  else if (T <= 19) hipLaunchKernelGGL((k_factor<WP, ftpw_for(19)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
-  else hipLaunchKernelGGL((k_factor<WP, ftpw_for(MAXT)>), dim3(wg), dim3(FNT), 0, st, *ls, Bw);
+  if (T <= 12) hipLaunchKernelGGL((k_factor<WP, ftpw_for(12)>), dim3(wg), dim3(FNT), 0, st, *ls);
+  else if (T <= 17) hipLaunchKernelGGL((k_factor<WP, ftpw_for(17)>), dim3(wg), dim3(FNT), 0, st, *ls);
+  else if (T <= 19) hipLaunchKernelGGL((k_factor<WP, ftpw_for(19)>), dim3(wg), dim3(FNT), 0, st, *ls);
+  else hipLaunchKernelGGL((k_factor<WP, ftpw_for(MAXT)>), dim3(wg), dim3(FNT), 0, st, *ls);
 }
 
-extern "C" hipError_t rxk_launch_factor(int wprec, const rxk::LaunchSet* ls, int wg, int Bw,
+extern "C" hipError_t rxk_launch_factor(int wprec, const rxk::LaunchSet* ls, int wg,
                                         hipStream_t st) {
   using namespace rxk;
   if (wg <= 0) return hipSuccess;
   switch (wprec) {
-    case P_F64: launch_factor_t<P_F64>(ls, wg, Bw, st); break;
-    case P_F32: launch_factor_t<P_F32>(ls, wg, Bw, st); break;
-    case P_BF16: launch_factor_t<P_BF16>(ls, wg, Bw, st); break;
-    case P_F16: launch_factor_t<P_F16>(ls, wg, Bw, st); break;
-    case P_FP8: launch_factor_t<P_FP8>(ls, wg, Bw, st); break;
+    case P_F64: launch_factor_t<P_F64>(ls, wg, st); break;
+    case P_F32: launch_factor_t<P_F32>(ls, wg, st); break;
+    case P_BF16: launch_factor_t<P_BF16>(ls, wg, st); break;
+    case P_F16: launch_factor_t<P_F16>(ls, wg, st); break;
+    case P_FP8: launch_factor_t<P_FP8>(ls, wg, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -27,7 +27,7 @@ using namespace rxk;
 
 extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const LaunchSet* ls, int wg,
                                        const LaunchSet* ls2, int wg2, hipStream_t st);
-extern "C" hipError_t rxk_launch_factor(int wprec, const LaunchSet* ls, int wg, int Bw, hipStream_t st);
+extern "C" hipError_t rxk_launch_factor(int wprec, const LaunchSet* ls, int wg, hipStream_t st);
 extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const LaunchSet* ls, int wg, int Bw,
                                         hipStream_t st);
 extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mode, double tau, int64_t k,
@@ -645,13 +645,15 @@ static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* 
                              return prof_mark(prof, 2, false, st);
                            });
   if (r != RX_OK) return r;
-  r = run_groups([](const Job& j) { return j.wp * 1024 + j.Bw; },
+  // one factor launch per whitening precision: each batch takes its own
+  // operand pitch, and the template is sized by the launch's largest band count
+  r = run_groups([](const Job& j) { return j.wp; },
                  [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
                    LaunchSet a;
                    const int n = fill(a, grp, g0, g1, &Job::wg_factor);
                    rx_status q;
                    if ((q = prof_mark(prof, 3, true, st)) != RX_OK) return q;
-                   HIPC(rxk_launch_factor(jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw, st));
+                   HIPC(rxk_launch_factor(jobs[grp[g0]].wp, &a, n, st));
                    return prof_mark(prof, 3, false, st);
                  });
   if (r != RX_OK) return r;
