@@ -269,12 +269,27 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
     const int Bw = 32 * ((Bp + 31) / 32);           // operand row pitch of this batch
     S* wl = static_cast<S*>(d.wlp) + (int64_t)b * Bp * Bw;
     __syncthreads();
-    if constexpr (LP) {           // row maxima of |W_ij 2^e_j|: one wave per row, lanes over columns
-      for (int i = wv; i < Bp; i += FNW) {
-        double m = 0.0;
-        for (int j = lane; j <= i && j < B; j += 64) m = fmax(m, fabs(ldexp(W[(int64_t)i * Bp + j], ek[j])));
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-        if (lane == 0) fi[i] = (m > 0.0) ? ilogb(m) - top : 0;
+    constexpr int NCC = (MAXBP + 63) / 64;        // 64-column chunks of a row
+    if constexpr (LP) {
+      // row maxima of |W_ij 2^e_j|: one wave per four rows, lanes over the
+      // columns, every load of the four rows independent (the maximum is exact
+      // in any order)
+      for (int i0 = 4 * wv; i0 < Bp; i0 += 4 * FNW) {
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < NCC; ++c) {
+          const int j = lane + 64 * c;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = i0 + q;
+            if (j <= i && j < B) m[q] = fmax(m[q], fabs(ldexp(W[(int64_t)i * Bp + j], ek[j])));
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          for (int o = 32; o > 0; o >>= 1) m[q] = fmax(m[q], __shfl_xor(m[q], o, 64));
+          if (lane == 0) fi[i0 + q] = (m[q] > 0.0) ? ilogb(m[q]) - top : 0;
+        }
       }
     } else {
       for (int k = tid; k < Bp; k += FNT) fi[k] = 0;
@@ -284,11 +299,18 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
       d.iscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, -ek[k]);
       d.oscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, fi[k]);
     }
-    // one wave per row, lanes over the columns of the row's lower tiles
-    for (int i = wv; i < Bp; i += FNW) {
-      const int jend = 16 * (i / 16 + 1);
-      for (int j = lane; j < jend; j += 64)
-        wl[(int64_t)i * Bw + j] = to_storage<WP>((float)ldexp(W[(int64_t)i * Bp + j], ek[j] - fi[i]));
+    // one wave per four rows, lanes over the columns of each row's lower tiles
+    for (int i0 = 4 * wv; i0 < Bp; i0 += 4 * FNW) {
+#pragma unroll
+      for (int c = 0; c < NCC; ++c) {
+        const int j = lane + 64 * c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = i0 + q;
+          if (j < 16 * (i / 16 + 1))
+            wl[(int64_t)i * Bw + j] = to_storage<WP>((float)ldexp(W[(int64_t)i * Bp + j], ek[j] - fi[i]));
+        }
+      }
     }
   }
   if (tid == 0) d.status[b] = 0;

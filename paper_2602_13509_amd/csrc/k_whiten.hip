@@ -178,6 +178,7 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
 //    over tile rows then over the four lane groups.
 constexpr int W2NT = 512;                     // 8 waves
 constexpr int W2W = W2NT / 64;
+constexpr int W2_FREE_CUS = 32;                // CUs the tile kernel leaves to other queues
 constexpr int W2G = 4;                        // 16-pixel products per tile
 constexpr int W2TP = 16 * W2G;                // pixels per tile
 constexpr int MAXS = (MAXT + 1) / 2;          // 32-band operand steps
@@ -480,14 +481,23 @@ struct TopkState {
   int all;
 };
 
+// Maximum score key: per-wave, then per-workgroup reduction, one atomic per
+// workgroup (the launch keeps the workgroup count small).
+constexpr int MAXKEY_WG = 512;
 __global__ void __launch_bounds__(NT) k_maxkey(const void* sc, int f64, int64_t n, uint64_t* out) {
+  __shared__ uint64_t wm[NT / 64];
   uint64_t m = 0;
   for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
     const double v = score_at(sc, f64, i);
     if (v == v) m = max(m, okey(v));
   }
   for (int o = 32; o > 0; o >>= 1) m = max(m, (uint64_t)__shfl_xor((unsigned long long)m, o, 64));
-  if ((threadIdx.x & 63) == 0 && m) atomicMax((unsigned long long*)out, (unsigned long long)m);
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; ++w) m = max(m, wm[w]);
+    if (m) atomicMax((unsigned long long*)out, (unsigned long long)m);
+  }
 }
 
 __global__ void __launch_bounds__(NT) k_mask_thr(const void* sc, int f64, int64_t n, double thr,
@@ -638,7 +648,11 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
       }
       const int ncu = (dev < 64 && cus[dev] > 0) ? cus[dev] : 256;
       const int64_t ntile = t.wg0[t.nb];
-      const int g = (int)std::max<int64_t>(1, std::min<int64_t>(ncu, ntile / (2 * W2W)));
+      // one persistent workgroup per CU fills a CU's registers and most of
+      // its LDS; leaving W2_FREE_CUS CUs out lets the next batch's merge and
+      // factorisation (queued on another HIP stream) run beside the whitening
+      const int navail = ncu > 4 * W2_FREE_CUS ? ncu - W2_FREE_CUS : ncu;
+      const int g = (int)std::max<int64_t>(1, std::min<int64_t>(navail, ntile / (2 * W2W)));
       switch ((wprec * 16 + ns) * 8 + G) {
 #define RXK_W2(PV, N, GG)                                                                              \
   case (PV * 16 + N) * 8 + GG:                                                                         \
@@ -688,7 +702,7 @@ extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mo
     hipLaunchKernelGGL(k_mask_thr, dim3(gw), dim3(NT), 0, st, sc, f64, n, tau, (const uint64_t*)nullptr, 0.0, bits);
   } else if (mode == 1) {
     hipLaunchKernelGGL(k_clear_key, dim3(1), dim3(64), 0, st, maxkey);
-    hipLaunchKernelGGL(k_maxkey, dim3(gs), dim3(NT), 0, st, sc, f64, n, maxkey);
+    hipLaunchKernelGGL(k_maxkey, dim3(gs < MAXKEY_WG ? gs : MAXKEY_WG), dim3(NT), 0, st, sc, f64, n, maxkey);
     hipLaunchKernelGGL(k_mask_thr, dim3(gw), dim3(NT), 0, st, sc, f64, n, 0.0, (const uint64_t*)maxkey, tau, bits);
   } else {
     hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, st, tk, k, hist);

@@ -63,7 +63,10 @@ struct DevBuf {
 static rx_status dev_ensure(DevBuf& b, size_t bytes, hipStream_t st) {
   if (bytes <= b.cap) return RX_OK;
   if (b.p) {
-    HIPC(hipStreamSynchronize(st));
+    // growing is rare (first push, larger batch); the old buffer may still be
+    // read on any of the stream's queues, so wait for the whole device
+    (void)st;
+    HIPC(hipDeviceSynchronize());
     HIPC(hipFree(b.p));
     b.p = nullptr;
     b.cap = 0;
@@ -87,9 +90,10 @@ static void dev_free(DevBuf& b) {
 static constexpr uint32_t kMagic = 0x52585354u;   // "RXST"
 static constexpr int kSplitChunks = 64;            // pixel chunks per covariance split, 64x64 super-tile kernel
 // Pixel chunks per covariance split, whole-triangle kernel (one workgroup per
-// CU): 84 makes a 100-line block of 640 samples 12 splits, so 20 such blocks
-// pushed together fill one pass of 256 CUs (240 workgroups, not 260).
-static constexpr int kSplitChunks2 = 84;
+// CU): 91 makes a 100-line block of 640 samples 11 splits, so 20 such blocks
+// pushed together take one pass of 220 CUs and leave room for the 20
+// factorisation workgroups of the previous push running beside them.
+static constexpr int kSplitChunks2 = 91;
 static constexpr int kMaxBlocksPerBatch = 64;      // reset bits are a 64-bit mask
 
 static int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -176,9 +180,15 @@ struct rx_stream {
   int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
   size_t esz = 0;
   int dev = 0;
-  hipStream_t st = nullptr;
+  // Three queues: A (centring shift, covariance product), B (merge,
+  // factorisation), st = C (whitening, masks, score pops).  One batch's
+  // factorisation and whitening overlap the next batch's product; served
+  // streams run everything on the server's single queue.
+  hipStream_t st = nullptr, stA = nullptr, stB = nullptr;
   bool own_st = false;
-  hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr;
+  hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr, ev_hcopy = nullptr;
+  hipEvent_t ev_a = nullptr, ev_fact = nullptr, ev_merged[2] = {nullptr, nullptr}, ev_white[2] = {nullptr, nullptr};
+  int npar = 1, par = 0, last_par = 0;    // parity sets of the per-batch buffers (queued batches alternate)
   rx_server* srv = nullptr;
   size_t footprint = 0;
   // resident window state (ping-pong)
@@ -187,7 +197,11 @@ struct rx_stream {
   int64_t N = 0;
   int64_t lines_seen = 0;
   // batch scratch
-  DevBuf shift, part, psum, mu, m2s, nsnap, w64, wlp, isc, osc, status, nsing, evb, dvb, coefb;
+  DevBuf m2s, nsnap, nsing, evb, dvb, coefb;
+  // by parity: a batch's product partials are read by its merge while the
+  // next batch's product runs; its mean snapshot, W, scales and status are
+  // read by its whitening while the next batch's merge and factor run
+  DevBuf shift[2], part[2], psum[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2];
   unsigned last_nsing = 0;
   // pending scores
   DevBuf pend[2];
@@ -294,9 +308,20 @@ extern "C" rx_status rx_stream_footprint(const rx_config* cfg, int32_t max_block
 }
 
 // ---------------------------------------------------------------------------- init / destroy
+// Wait for every queue of a stream (A and B feed C, but host reads of the
+// statistics, counters or W must not depend on that).
+static hipError_t sync_all(rx_stream* s) {
+  hipError_t e = hipStreamSynchronize(s->st);
+  if (e == hipSuccess && s->stA && s->stA != s->st) e = hipStreamSynchronize(s->stA);
+  if (e == hipSuccess && s->stB && s->stB != s->st) e = hipStreamSynchronize(s->stB);
+  return e;
+}
+
 static void free_stream(rx_stream* s) {
-  DevBuf* bufs[] = {&s->s1[0], &s->s1[1], &s->m2[0], &s->m2[1], &s->shift, &s->part, &s->psum, &s->mu,
-                    &s->m2s, &s->nsnap, &s->w64, &s->wlp, &s->isc, &s->osc, &s->status, &s->evb, &s->dvb, &s->coefb,
+  DevBuf* bufs[] = {&s->s1[0], &s->s1[1], &s->m2[0], &s->m2[1], &s->shift[0], &s->shift[1], &s->part[0],
+                    &s->part[1], &s->psum[0], &s->psum[1], &s->mu[0],
+                    &s->mu[1], &s->m2s, &s->nsnap, &s->w64[0], &s->w64[1], &s->wlp[0], &s->wlp[1], &s->isc[0],
+                    &s->isc[1], &s->osc[0], &s->osc[1], &s->status[0], &s->status[1], &s->evb, &s->dvb, &s->coefb,
                     &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
   for (DevBuf* b : bufs) dev_free(*b);
   if (s->host_pin) (void)hipHostFree(s->host_pin);
@@ -305,32 +330,47 @@ static void free_stream(rx_stream* s) {
   for (hipEvent_t e : s->prof_pool) (void)hipEventDestroy(e);
   s->prof_pool.clear();
   s->prof_open.clear();
-  if (s->ev_in) (void)hipEventDestroy(s->ev_in);
-  if (s->ev_done) (void)hipEventDestroy(s->ev_done);
-  if (s->ev_stage) (void)hipEventDestroy(s->ev_stage);
-  if (s->own_st && s->st) (void)hipStreamDestroy(s->st);
+  hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_a, s->ev_merged[0], s->ev_merged[1],
+                      s->ev_fact, s->ev_white[0], s->ev_white[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (s->own_st) {
+    if (s->st) (void)hipStreamDestroy(s->st);
+    if (s->stA) (void)hipStreamDestroy(s->stA);
+    if (s->stB) (void)hipStreamDestroy(s->stB);
+  }
   s->magic = 0;
 }
 
 static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   const Sizes z = scratch_sizes(s->B, s->S, s->sp, nblk, blk_lines);
   rx_status r;
-  if ((r = dev_ensure(s->shift, z.shift, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->part, z.part, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->psum, z.psum, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->mu, z.mu, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->m2s, z.m2, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->nsnap, z.nsnap, s->st)) != RX_OK) return r;
-  // the factor never writes above the diagonal tiles of W or its low-precision
-  // copy (nor the copy's padding columns): those stay as zeroed here
-  const size_t w_before = s->w64.cap, wl_before = s->wlp.cap;
-  if ((r = dev_ensure(s->w64, z.w64, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->wlp, z.wlp, s->st)) != RX_OK) return r;
-  if (s->w64.cap != w_before) HIPC(hipMemsetAsync(s->w64.p, 0, s->w64.cap, s->st));
-  if (s->wlp.cap != wl_before) HIPC(hipMemsetAsync(s->wlp.p, 0, s->wlp.cap, s->st));
-  if ((r = dev_ensure(s->isc, z.scl, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->osc, z.scl, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->status, z.status, s->st)) != RX_OK) return r;
+  bool zeroed = false;
+  for (int q = 0; q < s->npar; ++q) {
+    if ((r = dev_ensure(s->shift[q], z.shift, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->part[q], z.part, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->psum[q], z.psum, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->mu[q], z.mu, s->st)) != RX_OK) return r;
+    // the factor never writes above the diagonal tiles of W or its
+    // low-precision copy (nor the copy's padding columns): those stay as
+    // zeroed here
+    const size_t w_before = s->w64[q].cap, wl_before = s->wlp[q].cap;
+    if ((r = dev_ensure(s->w64[q], z.w64, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->wlp[q], z.wlp, s->st)) != RX_OK) return r;
+    if (s->w64[q].cap != w_before) { HIPC(hipMemsetAsync(s->w64[q].p, 0, s->w64[q].cap, s->st)); zeroed = true; }
+    if (s->wlp[q].cap != wl_before) { HIPC(hipMemsetAsync(s->wlp[q].p, 0, s->wlp[q].cap, s->st)); zeroed = true; }
+    if ((r = dev_ensure(s->isc[q], z.scl, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->osc[q], z.scl, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->status[q], z.status, s->st)) != RX_OK) return r;
+  }
+  // buffers zeroed on queue C must be clear before queue B's factor writes
+  // them (only after a growth: otherwise B must not wait behind C)
+  if (zeroed && s->stB != s->st) {
+    HIPC(hipEventRecord(s->ev_done, s->st));
+    HIPC(hipStreamWaitEvent(s->stB, s->ev_done, 0));
+  }
   if ((r = dev_ensure(s->evb, z.ev, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->dvb, z.ev, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->coefb, z.coef, s->st)) != RX_OK) return r;
@@ -383,14 +423,20 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
     s->srv = srv;
     s->footprint = need;
     s->st = srv->st;
+    s->stA = s->stB = s->st;
+    s->npar = 1;
   } else {
-    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipStreamCreate failed"));
     s->own_st = true;
+    if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->stA, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->stB, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(RX_E_DEVICE, "hipStreamCreate failed"));
+    s->npar = 2;
   }
-  if (hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_done, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_stage, hipEventDisableTiming) != hipSuccess)
-    return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
+  hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_a, &s->ev_merged[0],
+                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1]};
+  for (hipEvent_t* e : evs)
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
   const size_t s1b = (size_t)s->Bp * 8, m2b = (size_t)s->Bp * s->Bp * 8;
   for (int i = 0; i < 2; ++i) {
     if ((r = dev_ensure(s->s1[i], s1b, s->st)) != RX_OK) return bail(r);
@@ -415,7 +461,7 @@ extern "C" rx_status rx_destroy(rx_stream* s) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
   (void)hipSetDevice(s->dev);
-  (void)hipStreamSynchronize(s->st);
+  (void)sync_all(s);
   if (s->srv) {
     rx_server* srv = s->srv;
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -455,6 +501,7 @@ struct Job {
   rx_stream* s;
   BatchDesc d;
   int in_type, sp, wp, Bw;
+  int par;
   int wg_shift, wg_syrk, wg_merge, wg_mmat, wg_factor, wg_whiten;
 };
 
@@ -521,10 +568,12 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
     }
   }
   d.reset_bits = rb;
-  d.shift = static_cast<double*>(s->shift.p);
-  d.part = s->part.p;
-  d.psum = static_cast<double*>(s->psum.p);
-  d.mu_snap = static_cast<double*>(s->mu.p);
+  const int q = s->par;                     // parity set of this batch's buffers
+  j.par = q;
+  d.shift = static_cast<double*>(s->shift[q].p);
+  d.part = s->part[q].p;
+  d.psum = static_cast<double*>(s->psum[q].p);
+  d.mu_snap = static_cast<double*>(s->mu[q].p);
   d.m2_snap = static_cast<double*>(s->m2s.p);
   d.n_snap = static_cast<double*>(s->nsnap.p);
   d.ev = static_cast<double*>(s->evb.p);
@@ -534,11 +583,11 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.s1_out = static_cast<double*>(s->s1[1 - s->cur].p);
   d.m2_in = static_cast<const double*>(s->m2[s->cur].p);
   d.m2_out = static_cast<double*>(s->m2[1 - s->cur].p);
-  d.w64 = static_cast<double*>(s->w64.p);
-  d.wlp = s->wlp.p;
-  d.iscale = static_cast<float*>(s->isc.p);
-  d.oscale = static_cast<float*>(s->osc.p);
-  d.status = static_cast<int*>(s->status.p);
+  d.w64 = static_cast<double*>(s->w64[q].p);
+  d.wlp = s->wlp[q].p;
+  d.iscale = static_cast<float*>(s->isc[q].p);
+  d.oscale = static_cast<float*>(s->osc[q].p);
+  d.status = static_cast<int*>(s->status[q].p);
   d.nsing = static_cast<unsigned int*>(s->nsing.p);
   d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
 
@@ -557,6 +606,8 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   s->cur ^= 1;
   s->tail += npx;
   s->last_w_off = (int64_t)(nblk - 1) * s->Bp * s->Bp;
+  s->last_par = q;
+  s->par = (q + 1) % s->npar;
   s->cnt.blocks += nblk;
   return RX_OK;
 }
@@ -597,9 +648,23 @@ static rx_status prof_collect(rx_stream* s) {
   return RX_OK;
 }
 
-// Launch the five phases for a set of jobs (each stream at most once).
+// Launch the five phases for a set of jobs (each stream at most once) on the
+// queues of `pipe`: A (shift, covariance product), B (merge, factorisation),
+// C (whitening).  When the three differ (one unserved stream, one job) the
+// batch is ordered with events on its parity set of buffers:
+//   A waits for the merge that last read this parity's product partials
+//     (two batches back);
+//   B waits for A's product, and for the whitening that last read this
+//     parity's mean snapshot, W, scales and status;
+//   C waits for B's factorisation.
 // prof (nullable): stream whose phase timers bracket the launches.
-static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* prof = nullptr) {
+struct Queues {
+  hipStream_t A, B, C;
+};
+static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof = nullptr) {
+  const bool piped = qs.A != qs.C;
+  rx_stream* ps = piped ? jobs[0].s : nullptr;
+  if (piped && jobs.size() != 1) return fail(RX_E_STATE, "pipelined launch of several jobs");
   auto run_groups = [&](auto key, auto launch) -> rx_status {
     std::vector<bool> done(jobs.size(), false);
     for (size_t a = 0; a < jobs.size(); ++a) {
@@ -625,6 +690,7 @@ static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* 
     }
     return ls.wg0[ls.nb];
   };
+  if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_merged[jobs[0].par], 0));
   rx_status r = run_groups([](const Job& j) { return j.in_type * 16 + j.sp; },
                            [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
                              LaunchSet a, b, c, e;
@@ -634,15 +700,22 @@ static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* 
                              const int n4 = fill(e, grp, g0, g1, &Job::wg_mmat);
                              const int it = jobs[grp[g0]].in_type, sp = jobs[grp[g0]].sp;
                              rx_status q;
-                             if ((q = prof_mark(prof, 0, true, st)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, 0, &a, n1, nullptr, 0, st));
-                             if ((q = prof_mark(prof, 0, false, st)) != RX_OK) return q;
-                             if ((q = prof_mark(prof, 1, true, st)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, st));
-                             if ((q = prof_mark(prof, 1, false, st)) != RX_OK) return q;
-                             if ((q = prof_mark(prof, 2, true, st)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, st));
-                             return prof_mark(prof, 2, false, st);
+                             if ((q = prof_mark(prof, 0, true, qs.A)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, 0, &a, n1, nullptr, 0, qs.A));
+                             if ((q = prof_mark(prof, 0, false, qs.A)) != RX_OK) return q;
+                             if ((q = prof_mark(prof, 1, true, qs.A)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, qs.A));
+                             if ((q = prof_mark(prof, 1, false, qs.A)) != RX_OK) return q;
+                             if (piped) {
+                               HIPC(hipEventRecord(ps->ev_a, qs.A));
+                               HIPC(hipStreamWaitEvent(qs.B, ps->ev_a, 0));
+                               HIPC(hipStreamWaitEvent(qs.B, ps->ev_white[jobs[0].par], 0));
+                             }
+                             if ((q = prof_mark(prof, 2, true, qs.B)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, qs.B));
+                             if ((q = prof_mark(prof, 2, false, qs.B)) != RX_OK) return q;
+                             if (piped) HIPC(hipEventRecord(ps->ev_merged[jobs[0].par], qs.B));
+                             return RX_OK;
                            });
   if (r != RX_OK) return r;
   // one factor launch per whitening precision: each batch takes its own
@@ -652,26 +725,38 @@ static rx_status launch_jobs(std::vector<Job>& jobs, hipStream_t st, rx_stream* 
                    LaunchSet a;
                    const int n = fill(a, grp, g0, g1, &Job::wg_factor);
                    rx_status q;
-                   if ((q = prof_mark(prof, 3, true, st)) != RX_OK) return q;
-                   HIPC(rxk_launch_factor(jobs[grp[g0]].wp, &a, n, st));
-                   return prof_mark(prof, 3, false, st);
+                   if ((q = prof_mark(prof, 3, true, qs.B)) != RX_OK) return q;
+                   HIPC(rxk_launch_factor(jobs[grp[g0]].wp, &a, n, qs.B));
+                   return prof_mark(prof, 3, false, qs.B);
                  });
   if (r != RX_OK) return r;
-  return run_groups([](const Job& j) { return (j.in_type * 16 + j.wp) * 1024 + j.Bw; },
-                    [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
-                      LaunchSet a;
-                      const int n = fill(a, grp, g0, g1, &Job::wg_whiten);
-                      rx_status q;
-                      if ((q = prof_mark(prof, 4, true, st)) != RX_OK) return q;
-                      HIPC(rxk_launch_whiten(jobs[grp[g0]].in_type, jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw, st));
-                      return prof_mark(prof, 4, false, st);
-                    });
+  if (piped) {
+    HIPC(hipEventRecord(ps->ev_fact, qs.B));
+    HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+  }
+  r = run_groups([](const Job& j) { return (j.in_type * 16 + j.wp) * 1024 + j.Bw; },
+                 [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
+                   LaunchSet a;
+                   const int n = fill(a, grp, g0, g1, &Job::wg_whiten);
+                   rx_status q;
+                   if ((q = prof_mark(prof, 4, true, qs.C)) != RX_OK) return q;
+                   HIPC(rxk_launch_whiten(jobs[grp[g0]].in_type, jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw, qs.C));
+                   return prof_mark(prof, 4, false, qs.C);
+                 });
+  if (r != RX_OK) return r;
+  if (piped) HIPC(hipEventRecord(ps->ev_white[jobs[0].par], qs.C));
+  return RX_OK;
 }
 
 // ---------------------------------------------------------------------------- push
+// Host lines go through one pinned buffer and one device staging buffer:
+// the pinned buffer is refilled once the previous copy out of it is done
+// (ev_hcopy, host wait); the staging buffer is overwritten on queue A only
+// after the previous push's whitening, the last reader, is done (ev_stage).
 static rx_status stage_host_input(rx_stream* s, const void* lines, size_t bytes, const void** x) {
   if (s->stage_busy) {
-    HIPC(hipEventSynchronize(s->ev_stage));
+    HIPC(hipEventSynchronize(s->ev_hcopy));
+    HIPC(hipStreamWaitEvent(s->stA, s->ev_stage, 0));
     s->stage_busy = false;
   }
   if (bytes > s->host_pin_cap) {
@@ -687,8 +772,8 @@ static rx_status stage_host_input(rx_stream* s, const void* lines, size_t bytes,
   rx_status r = dev_ensure(s->stage, bytes, s->st);
   if (r != RX_OK) return r;
   std::memcpy(s->host_pin, lines, bytes);
-  HIPC(hipMemcpyAsync(s->stage.p, s->host_pin, bytes, hipMemcpyHostToDevice, s->st));
-  HIPC(hipEventRecord(s->ev_stage, s->st));
+  HIPC(hipMemcpyAsync(s->stage.p, s->host_pin, bytes, hipMemcpyHostToDevice, s->stA));
+  HIPC(hipEventRecord(s->ev_hcopy, s->stA));
   s->stage_busy = true;
   *x = s->stage.p;
   return RX_OK;
@@ -708,7 +793,7 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     if ((r = stage_host_input(s, lines, bytes, &x)) != RX_OK) return r;
   } else {
     HIPC(hipEventRecord(s->ev_in, static_cast<hipStream_t>(hip_stream)));
-    HIPC(hipStreamWaitEvent(s->st, s->ev_in, 0));
+    HIPC(hipStreamWaitEvent(s->stA, s->ev_in, 0));   // queues B and C follow A by events
   }
   std::vector<Block> blks;
   cut_blocks(s, s->lines_seen, n_lines, blks);
@@ -720,9 +805,10 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     if (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines < blks[i].lines) ++k;
     std::vector<Job> jobs(1);
     if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready)) != RX_OK) return r;
-    if ((r = launch_jobs(jobs, s->st, s)) != RX_OK) return r;
+    if ((r = launch_jobs(jobs, Queues{s->stA, s->stB, s->st}, s)) != RX_OK) return r;
     i = k;
   }
+  if (!is_device_ptr) HIPC(hipEventRecord(s->ev_stage, s->st));   // last reader of the staging buffer
   s->lines_seen += n_lines;
   s->cnt.lines_pushed += n_lines;
   if (notready) return fail(RX_E_NOTREADY, "a block was scored with N <= B and no ridge; its scores are NaN");
@@ -818,7 +904,7 @@ extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, 
 // ---------------------------------------------------------------------------- sync / counters / hooks
 static rx_status refresh_counters(rx_stream* s) {
   HIPC(hipSetDevice(s->dev));
-  HIPC(hipStreamSynchronize(s->st));
+  HIPC(sync_all(s));
   unsigned ns = 0;
   HIPC(hipMemcpy(&ns, s->nsing.p, sizeof ns, hipMemcpyDeviceToHost));
   if (ns > s->last_nsing && s->sticky == RX_OK) s->sticky = RX_E_SINGULAR;
@@ -863,7 +949,7 @@ extern "C" rx_status rx_profile(rx_stream* s, int32_t enable) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
   HIPC(hipSetDevice(s->dev));
-  HIPC(hipStreamSynchronize(s->st));
+  HIPC(sync_all(s));
   if ((r = prof_collect(s)) != RX_OK) return r;
   s->prof = enable != 0;
   for (int i = 0; i < 5; ++i) { s->prof_ms[i] = 0.0; s->prof_n[i] = 0; }
@@ -875,7 +961,7 @@ extern "C" rx_status rx_phase_times(rx_stream* s, double* ms, int64_t* launches)
   if (r != RX_OK) return r;
   if (!ms || !launches) return fail(RX_E_ARG, "null output");
   HIPC(hipSetDevice(s->dev));
-  HIPC(hipStreamSynchronize(s->st));
+  HIPC(sync_all(s));
   if ((r = prof_collect(s)) != RX_OK) return r;
   for (int i = 0; i < 5; ++i) { ms[i] = s->prof_ms[i]; launches[i] = s->prof_n[i]; }
   return RX_OK;
@@ -886,7 +972,7 @@ extern "C" rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double
   if (r != RX_OK) return r;
   if (!n) return fail(RX_E_ARG, "null n");
   HIPC(hipSetDevice(s->dev));
-  HIPC(hipStreamSynchronize(s->st));
+  HIPC(sync_all(s));
   const int B = s->B, Bp = s->Bp;
   std::vector<double> s1(Bp), m2((size_t)Bp * Bp);
   HIPC(hipMemcpy(s1.data(), s->s1[s->cur].p, (size_t)Bp * 8, hipMemcpyDeviceToHost));
@@ -908,7 +994,7 @@ extern "C" rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, c
   if (n < 0 || (n > 0 && (!mean || !cov))) return fail(RX_E_ARG, "bad statistics");
   if (n > 0 && n <= s->cfg.ddof) return fail(RX_E_ARG, "n must exceed ddof");
   HIPC(hipSetDevice(s->dev));
-  HIPC(hipStreamSynchronize(s->st));
+  HIPC(sync_all(s));
   const int B = s->B, Bp = s->Bp;
   std::vector<double> s1(Bp, 0.0), m2((size_t)Bp * Bp, 0.0);
   if (n > 0) {
@@ -929,10 +1015,11 @@ extern "C" rx_status rx_get_whitener(rx_stream* s, double* w) {
   if (!w) return fail(RX_E_ARG, "null output");
   if (s->last_w_off < 0) return fail(RX_E_STATE, "no block has been factored yet");
   HIPC(hipSetDevice(s->dev));
-  HIPC(hipStreamSynchronize(s->st));
+  HIPC(sync_all(s));
   const int B = s->B, Bp = s->Bp;
   std::vector<double> full((size_t)Bp * Bp);
-  HIPC(hipMemcpy(full.data(), static_cast<double*>(s->w64.p) + s->last_w_off, full.size() * 8, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(full.data(), static_cast<double*>(s->w64[s->last_par].p) + s->last_w_off, full.size() * 8,
+                 hipMemcpyDeviceToHost));
   for (int i = 0; i < B; ++i)
     for (int j = 0; j < B; ++j) w[(size_t)i * B + j] = full[(size_t)i * Bp + j];
   return RX_OK;
@@ -1019,7 +1106,7 @@ extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
     s->cnt.lines_pushed += take[i].lines;
     f.items.push_back({s, take[i].tag});
   }
-  rx_status r = launch_jobs(jobs, srv->st);
+  rx_status r = launch_jobs(jobs, Queues{srv->st, srv->st, srv->st});
   if (r != RX_OK) return r;
   if (srv->free_events.empty()) {
     hipEvent_t e;

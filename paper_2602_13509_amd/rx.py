@@ -150,21 +150,25 @@ class RxStream:
         self.score_f64 = cfg.whiten_prec == RX_FP64
 
     # -- core path
-    def rx_push_lines(self, lines, stream=None, allow_notready=True) -> int:
+    def rx_push_lines(self, lines, stream=None, allow_notready=True, guard=True) -> int:
         """lines: BIL [n_lines][B][S] torch tensor (device or host) or numpy array.
 
-        A device tensor is read asynchronously by the library's own HIP
-        stream; the caller's stream (torch's current one by default) is then
-        made to wait for that work (rx_wait, no host block), so later work on
-        it -- including torch's reuse of the tensor's memory once it is
-        freed -- cannot overwrite the lines before they are read."""
+        A device tensor is read asynchronously on the library's own queues,
+        after the work already on the caller's stream (torch's current one by
+        default).  With guard=True the caller's stream is then made to wait
+        for that work (rx_wait, no host block), so later work on it --
+        including torch's reuse of the tensor's memory once it is freed --
+        cannot overwrite the lines before they are read.  guard=False leaves
+        the caller's stream free (so one push's tail can overlap the next
+        push): the tensor must then stay alive and unchanged until rx_sync or
+        an rx_wait, as the C interface states."""
         n = lines.shape[0]
         assert tuple(lines.shape[1:]) == (self.B, self.S), lines.shape
         dev = _is_dev(lines)
         sh = _stream_handle(stream) if dev else 0
         r = check(LIB.rx_push_lines(self.h, _ptr(lines), n, dev, sh),
                   allow=(RX_E_NOTREADY,) if allow_notready else ())
-        if dev:
+        if dev and guard:
             check(LIB.rx_wait(self.h, sh))
         return r
 
