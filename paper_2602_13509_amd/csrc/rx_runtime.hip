@@ -180,14 +180,14 @@ struct rx_stream {
   int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
   size_t esz = 0;
   int dev = 0;
-  // Three queues: A (centring shift, covariance product), B (merge,
+  // Three queues: A (centring shift, covariance product, merge), B (FP64
   // factorisation), st = C (whitening, masks, score pops).  One batch's
-  // factorisation and whitening overlap the next batch's product; served
-  // streams run everything on the server's single queue.
+  // factorisation and whitening overlap the next batch's product and merge;
+  // served streams run everything on the server's single queue.
   hipStream_t st = nullptr, stA = nullptr, stB = nullptr;
   bool own_st = false;
   hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr, ev_hcopy = nullptr;
-  hipEvent_t ev_a = nullptr, ev_fact = nullptr, ev_merged[2] = {nullptr, nullptr}, ev_white[2] = {nullptr, nullptr};
+  hipEvent_t ev_fact = nullptr, ev_merged[2] = {nullptr, nullptr}, ev_white[2] = {nullptr, nullptr};
   int npar = 1, par = 0, last_par = 0;    // parity sets of the per-batch buffers (queued batches alternate)
   rx_server* srv = nullptr;
   size_t footprint = 0;
@@ -197,11 +197,11 @@ struct rx_stream {
   int64_t N = 0;
   int64_t lines_seen = 0;
   // batch scratch
-  DevBuf m2s, nsnap, nsing, evb, dvb, coefb;
-  // by parity: a batch's product partials are read by its merge while the
-  // next batch's product runs; its mean snapshot, W, scales and status are
-  // read by its whitening while the next batch's merge and factor run
-  DevBuf shift[2], part[2], psum[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2];
+  DevBuf nsing, evb, dvb, coefb, shift, part, psum;
+  // by parity: a batch's M2 and count snapshots are read by its factor, and
+  // its mean snapshot, W, scales and status by its whitening, while the next
+  // batch's product and merge run on queue A
+  DevBuf m2s[2], nsnap[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2];
   unsigned last_nsing = 0;
   // pending scores
   DevBuf pend[2];
@@ -318,9 +318,9 @@ static hipError_t sync_all(rx_stream* s) {
 }
 
 static void free_stream(rx_stream* s) {
-  DevBuf* bufs[] = {&s->s1[0], &s->s1[1], &s->m2[0], &s->m2[1], &s->shift[0], &s->shift[1], &s->part[0],
-                    &s->part[1], &s->psum[0], &s->psum[1], &s->mu[0],
-                    &s->mu[1], &s->m2s, &s->nsnap, &s->w64[0], &s->w64[1], &s->wlp[0], &s->wlp[1], &s->isc[0],
+  DevBuf* bufs[] = {&s->s1[0], &s->s1[1], &s->m2[0], &s->m2[1], &s->shift, &s->part, &s->psum, &s->m2s[1],
+                    &s->nsnap[1], &s->mu[0],
+                    &s->mu[1], &s->m2s[0], &s->nsnap[0], &s->w64[0], &s->w64[1], &s->wlp[0], &s->wlp[1], &s->isc[0],
                     &s->isc[1], &s->osc[0], &s->osc[1], &s->status[0], &s->status[1], &s->evb, &s->dvb, &s->coefb,
                     &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
   for (DevBuf* b : bufs) dev_free(*b);
@@ -330,7 +330,7 @@ static void free_stream(rx_stream* s) {
   for (hipEvent_t e : s->prof_pool) (void)hipEventDestroy(e);
   s->prof_pool.clear();
   s->prof_open.clear();
-  hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_a, s->ev_merged[0], s->ev_merged[1],
+  hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_merged[0], s->ev_merged[1],
                       s->ev_fact, s->ev_white[0], s->ev_white[1]};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
@@ -345,13 +345,13 @@ static void free_stream(rx_stream* s) {
 static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   const Sizes z = scratch_sizes(s->B, s->S, s->sp, nblk, blk_lines);
   rx_status r;
-  if ((r = dev_ensure(s->m2s, z.m2, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->nsnap, z.nsnap, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->shift, z.shift, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->part, z.part, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->psum, z.psum, s->st)) != RX_OK) return r;
   bool zeroed = false;
   for (int q = 0; q < s->npar; ++q) {
-    if ((r = dev_ensure(s->shift[q], z.shift, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->part[q], z.part, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->psum[q], z.psum, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->m2s[q], z.m2, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->nsnap[q], z.nsnap, s->st)) != RX_OK) return r;
     if ((r = dev_ensure(s->mu[q], z.mu, s->st)) != RX_OK) return r;
     // the factor never writes above the diagonal tiles of W or its
     // low-precision copy (nor the copy's padding columns): those stay as
@@ -433,7 +433,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
       return bail(fail(RX_E_DEVICE, "hipStreamCreate failed"));
     s->npar = 2;
   }
-  hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_a, &s->ev_merged[0],
+  hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_merged[0],
                        &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1]};
   for (hipEvent_t* e : evs)
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
@@ -570,12 +570,12 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.reset_bits = rb;
   const int q = s->par;                     // parity set of this batch's buffers
   j.par = q;
-  d.shift = static_cast<double*>(s->shift[q].p);
-  d.part = s->part[q].p;
-  d.psum = static_cast<double*>(s->psum[q].p);
+  d.shift = static_cast<double*>(s->shift.p);
+  d.part = s->part.p;
+  d.psum = static_cast<double*>(s->psum.p);
   d.mu_snap = static_cast<double*>(s->mu[q].p);
-  d.m2_snap = static_cast<double*>(s->m2s.p);
-  d.n_snap = static_cast<double*>(s->nsnap.p);
+  d.m2_snap = static_cast<double*>(s->m2s[q].p);
+  d.n_snap = static_cast<double*>(s->nsnap[q].p);
   d.ev = static_cast<double*>(s->evb.p);
   d.dv = static_cast<double*>(s->dvb.p);
   d.coef = static_cast<double*>(s->coefb.p);
@@ -649,14 +649,14 @@ static rx_status prof_collect(rx_stream* s) {
 }
 
 // Launch the five phases for a set of jobs (each stream at most once) on the
-// queues of `pipe`: A (shift, covariance product), B (merge, factorisation),
-// C (whitening).  When the three differ (one unserved stream, one job) the
+// queues `qs`: A (shift, covariance product, merge), B (factorisation), C
+// (whitening).  When the three differ (one unserved stream, one job) the
 // batch is ordered with events on its parity set of buffers:
-//   A waits for the merge that last read this parity's product partials
-//     (two batches back);
-//   B waits for A's product, and for the whitening that last read this
-//     parity's mean snapshot, W, scales and status;
-//   C waits for B's factorisation.
+//   A runs shift, product and merge in order; before the merge it waits for
+//     the whitening that last read this parity's snapshots (two batches
+//     back; that whitening followed the factor that read the M2 snapshot);
+//   B waits for A's merge, then factors;
+//   C waits for B's factorisation, then whitens.
 // prof (nullable): stream whose phase timers bracket the launches.
 struct Queues {
   hipStream_t A, B, C;
@@ -690,7 +690,6 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
     }
     return ls.wg0[ls.nb];
   };
-  if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_merged[jobs[0].par], 0));
   rx_status r = run_groups([](const Job& j) { return j.in_type * 16 + j.sp; },
                            [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
                              LaunchSet a, b, c, e;
@@ -706,15 +705,14 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                              if ((q = prof_mark(prof, 1, true, qs.A)) != RX_OK) return q;
                              HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, qs.A));
                              if ((q = prof_mark(prof, 1, false, qs.A)) != RX_OK) return q;
+                             if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par], 0));
+                             if ((q = prof_mark(prof, 2, true, qs.A)) != RX_OK) return q;
+                             HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, qs.A));
+                             if ((q = prof_mark(prof, 2, false, qs.A)) != RX_OK) return q;
                              if (piped) {
-                               HIPC(hipEventRecord(ps->ev_a, qs.A));
-                               HIPC(hipStreamWaitEvent(qs.B, ps->ev_a, 0));
-                               HIPC(hipStreamWaitEvent(qs.B, ps->ev_white[jobs[0].par], 0));
+                               HIPC(hipEventRecord(ps->ev_merged[jobs[0].par], qs.A));
+                               HIPC(hipStreamWaitEvent(qs.B, ps->ev_merged[jobs[0].par], 0));
                              }
-                             if ((q = prof_mark(prof, 2, true, qs.B)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, qs.B));
-                             if ((q = prof_mark(prof, 2, false, qs.B)) != RX_OK) return q;
-                             if (piped) HIPC(hipEventRecord(ps->ev_merged[jobs[0].par], qs.B));
                              return RX_OK;
                            });
   if (r != RX_OK) return r;
