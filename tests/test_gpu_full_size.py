@@ -1,0 +1,107 @@
+"""Full-size parity on sampled pixels, through the C ABI.
+
+* The 2000 x 640 x 270 uint16 sensor cube in the launch configuration the
+  benchmark times: one push of the whole cube cut into 20 blocks of 100
+  lines, cumulative window over the cube, update then score.  The oracle
+  takes exact integer moments of every block, forms each block's window
+  statistics exactly, and scores a sample of each block's pixels with an LU
+  solve.  FP64 path: tolerance of the FP64 scoring tests; BF16 path with the
+  1e-6 ridge: the BF16 tolerance (max 5e-2, p99 1e-2).
+* The 5000 x 1024 x 300 float32 stress cube (condition number 1e6, band
+  range 1e3) as one block: FP64 statistics, then FP64 whitening (tolerance
+  1e-7 / 1e-9) and FP16 / FP8 whitening, whose scores are checked against the
+  host emulation of the same quantisation and reported against the oracle.
+Both generate their cubes on the host (tens of seconds) and are marked slow.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import assert_scores, err_summary, say
+from oracle import rx as orx
+from oracle.stream import float_stats_chunked
+from paper_2602_13509_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def rxm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_13509_amd import rx
+    return rx
+
+
+def test_sensor_cube_full_size_sampled(rxm):
+    import torch
+    L, S, B, BL = 2000, 640, 270, 100
+    cube = synth.sensor_cube(0, lines=L, samples=S, bands=B).cube
+    x = torch.from_numpy(cube).cuda()
+    got = {}
+    for prec, rho in (("fp64", 0.0), ("bf16", 1e-6)):
+        st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk=prec, whiten=prec, ridge_rel=rho,
+                                          block_lines=BL, window_lines=L))
+        st.rx_push_lines(x)
+        st.rx_sync()
+        got[prec] = st.scores_host(f64=(prec == "fp64"))
+        st.rx_destroy()
+    rng = np.random.default_rng(5)
+    n = 0
+    s1 = np.zeros(B, dtype=object)
+    s2 = np.zeros((B, B), dtype=object)
+    idx, ref64, refbf = [], [], []
+    for b in range(L // BL):
+        px = orx.pixels(cube[b * BL:(b + 1) * BL])
+        nb, t1, t2 = orx.int_moments(px)
+        n += nb
+        s1 = s1 + t1.astype(object)
+        s2 = s2 + t2.astype(object)
+        mu, cov = orx.cov_from_int_moments(n, s1, s2)
+        pick = np.sort(rng.choice(px.shape[0], 400, replace=False))
+        idx.append(b * BL * S + pick)
+        ref64.append(orx.scores(px[pick], mu, cov))
+        refbf.append(orx.scores(px[pick], mu, orx.regularise(cov, 1e-6)))
+    idx = np.concatenate(idx)
+    say(f"sensor full size: {idx.size} sampled pixels over 20 blocks")
+    assert_scores(got["fp64"][idx], np.concatenate(ref64), B, 1e-9, 1e-11, "sensor full fp64")
+    assert_scores(got["bf16"][idx], np.concatenate(refbf), B, 5e-2, 1e-2, "sensor full bf16")
+
+
+def test_stress_cube_full_size_sampled(rxm):
+    import torch
+    from lowp_emu import emulate_scores
+    L, S, B = 5000, 1024, 300
+    sc = synth.stress_cube(0, lines=L, samples=S, bands=B)
+    cube = sc.cube
+    x = torch.from_numpy(cube).cuda()
+
+    def chunks():
+        for l0 in range(0, L, 250):
+            yield orx.pixels(cube[l0:l0 + 250])
+
+    n, mu, cov = float_stats_chunked(chunks)
+    rng = np.random.default_rng(6)
+    idx = np.sort(rng.choice(L * S, 4000, replace=False))
+    lines, samples = idx // S, idx % S
+    px = cube[lines, :, samples].astype(np.float64)          # [n_sample][B]
+    ref = orx.scores(px, mu, cov)
+
+    out = {}
+    for w in ("fp64", "fp16", "fp8"):
+        st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.float32, syrk="fp64", whiten=w))
+        st.rx_push_lines(x)
+        st.rx_sync()
+        out[w] = st.scores_host(f64=(w == "fp64"))[idx]
+        if w != "fp64":
+            wmat = st.rx_get_whitener()
+            n2, mean, cov2 = st.rx_get_stats()
+            emu, scale = emulate_scores(px, mean, cov2, wmat, w, with_scale=True)
+            bound = 2.0 * 1024 * 2.0 ** -24 * scale + 1e-6 * np.maximum(emu, 1e-3 * B)
+            e = np.abs(out[w] - emu)
+            mx, p99 = err_summary(out[w], ref, B)
+            say(f"stress full size {w}: vs oracle max rel {mx:.3e}, p99 rel {p99:.3e} (reported); "
+                f"vs emulation max |diff|/bound {np.max(e / bound):.3e}")
+            assert np.all(np.isfinite(out[w]))
+            assert np.all(e <= bound)
+        st.rx_destroy()
+    assert_scores(out["fp64"], ref, B, 1e-7, 1e-9, "stress full fp64")
