@@ -346,10 +346,12 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
 // 16-byte segments are stored XOR-swizzled (slot = segment ^ (r & 7)) so
 // the 16-row fragment reads hit distinct banks; each thread converts its own
 // slots in place (centred in FP32, rounded to the operand format) and keeps
-// the exact raw band sums.  Every wave issues the same loads for every chunk,
-// so waiting for a chunk is a fixed count of outstanding loads.
+// the exact raw band sums.  Every wave issues exactly S2IT loads per chunk,
+// also for rounds past the band count, so waiting for a chunk is a fixed
+// count of outstanding loads that the compiler can follow slot by slot.
 typedef __attribute__((ext_vector_type(2))) unsigned short u16x2;
-constexpr int S3ROWS = 16 * MAXT;          // rows per ring buffer
+constexpr int S3ROWS = 16 * MAXT;          // band rows (shift table)
+constexpr int S3RING = 128 * S2IT;         // rows per ring buffer: S2IT rounds of 128
 
 // Workgroup barrier that orders LDS accesses only.  A plain __syncthreads()
 // also waits for every outstanding global access of the wave, which would
@@ -366,9 +368,9 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   static_assert(M::KV == 8 && sizeof(S) == 2, "16-bit operand formats only");
   // three distinct LDS objects, used in a statically known rotation, so the
   // compiler tracks the in-flight direct loads of each one separately
-  __shared__ __attribute__((aligned(16))) uint16_t ring0[S3ROWS * KC];
-  __shared__ __attribute__((aligned(16))) uint16_t ring1[S3ROWS * KC];
-  __shared__ __attribute__((aligned(16))) uint16_t ring2[S3ROWS * KC];
+  __shared__ __attribute__((aligned(16))) uint16_t ring0[S3RING * KC];
+  __shared__ __attribute__((aligned(16))) uint16_t ring1[S3RING * KC];
+  __shared__ __attribute__((aligned(16))) uint16_t ring2[S3RING * KC];
   __shared__ float shl[S3ROWS];
 
   int local;
@@ -389,8 +391,9 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   // Round q of a chunk: wave wv loads rows 128 q + 8 wv + lrow, lane slot
   // lslot holding segment lslot ^ lrow (r & 7 == lrow).  Addresses are a
   // wave-uniform line base plus a 32-bit per-lane offset; lanes past the band
-  // count or the row end load the line's first word (in bounds) and the
-  // conversion writes zeros over their slot.
+  // count or the row end load the line's first word (in bounds).  Rows below
+  // the padded band count get zeros from the conversion; rows past it are
+  // read only by products whose tiles are never stored.
   const int segc = lslot ^ lrow;
   const uint32_t loff = 2u * ((uint32_t)(8 * wv + lrow) * (uint32_t)d.S + 8u * (uint32_t)segc);
   const uint32_t qstep = 2u * 128u * (uint32_t)d.S;
@@ -401,18 +404,13 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
     const char* lb = reinterpret_cast<const char*>(xb + (int64_t)line * d.B * d.S + s0);
 #pragma unroll
     for (int q = 0; q < S2IT; ++q) {
-      const int r0 = 128 * q + 8 * wv;           // wave-uniform
-      if (r0 < d.Bp) {
-        const bool ok = (r0 + lrow < d.B) && (8 * segc < nvalid);
-        const uint32_t off = ok ? loff + (uint32_t)q * qstep : 0u;
-        __builtin_amdgcn_global_load_lds((const void*)(lb + off),
-                                         (__attribute__((address_space(3))) void*)(buf + r0 * KC), 16, 0, 0);
-      }
+      const int r0 = 128 * q + 8 * wv;           // wave-uniform, < S3RING
+      const bool ok = (r0 + lrow < d.B) && (8 * segc < nvalid);
+      const uint32_t off = ok ? loff + (uint32_t)q * qstep : 0u;
+      __builtin_amdgcn_global_load_lds((const void*)(lb + off),
+                                       (__attribute__((address_space(3))) void*)(buf + r0 * KC), 16, 0, 0);
     }
   };
-  int nld = 0;                                   // direct loads per chunk of this wave
-#pragma unroll
-  for (int q = 0; q < S2IT; ++q) nld += (128 * q + 8 * wv < d.Bp) ? 1 : 0;
 
   uint32_t rawsum[S2IT];
 #pragma unroll
@@ -420,29 +418,33 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   for (int r = tid; r < d.Bp; r += S2NT) shl[r] = (r < d.B) ? (float)d.shift[(int64_t)b * d.Bp + r] : 0.0f;
   // the direct path runs only when the sample count is a multiple of 8, so an
   // 8-sample segment is either wholly inside the row or wholly past its end
-  // Per 32-bit word (two samples): two converts, two subtractions, one
-  // packed rounding, and the exact raw sum by a 16-bit dot product with
-  // (1, 1); items outside the rows or past the row end become zeros.
+  // Per 32-bit word (two samples): two conversions and two subtractions in
+  // FP32 (exact for any 16-bit count), one packed rounding to the operand
+  // format, and the exact raw sum by a 16-bit dot product with (1, 1).  Rounds whose 8 rows all lie inside the band count,
+  // in chunks without a ragged end, need no masking (a wave-uniform test);
+  // elsewhere items outside become raw 0 with shift 0 and so convert to +0.
   auto convert = [&](int ch, uint16_t* buf) {
     const int s0 = (int)((unsigned)ch % (unsigned)d.cpl) * KC;
     const int nvalid = min(KC, d.S - s0);
 #pragma unroll
     for (int q = 0; q < S2IT; ++q) {
-      const int it = tid + S2NT * q;
-      const int r = it >> 3, slot = it & 7;
-      if (r >= d.Bp) continue;
-      const int seg = slot ^ (r & 7);
-      const bool ok = (r < d.B) && (8 * seg < nvalid);
-      uint4* p = reinterpret_cast<uint4*>(buf + r * KC + 8 * slot);
-      const uint4 wv4 = *p;
-      const uint32_t wd[4] = {ok ? wv4.x : 0u, ok ? wv4.y : 0u, ok ? wv4.z : 0u, ok ? wv4.w : 0u};
-      const float sh = shl[r];
+      const int rb = 128 * q + 8 * wv;           // first row of the wave's round (uniform)
+      if (rb >= d.Bp) continue;
+      const int r = rb + lrow;
+      uint4* p = reinterpret_cast<uint4*>(buf + r * KC + 8 * lslot);
+      uint4 wv4 = *p;
+      float sh = shl[r];
+      if (!(rb + 8 <= d.B && nvalid == KC)) {
+        const bool ok = (r < d.B) && (8 * (lslot ^ lrow) < nvalid);
+        wv4 = ok ? wv4 : uint4{0u, 0u, 0u, 0u};
+        sh = ok ? sh : 0.0f;
+      }
+      const uint32_t wd[4] = {wv4.x, wv4.y, wv4.z, wv4.w};
       uint32_t o[4];
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
-        const float c0 = (float)(wd[h] & 0xffffu) - sh, c1 = (float)(wd[h] >> 16) - sh;
-        o[h] = ok ? cvt_pack2<P>(c0, c1) : 0u;
         rawsum[q] = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, wd[h]), u16x2{1, 1}, rawsum[q], false);
+        o[h] = cvt_pack2<P>((float)(wd[h] & 0xffffu) - sh, (float)(wd[h] >> 16) - sh);
       }
       *p = uint4{o[0], o[1], o[2], o[3]};
     }
@@ -484,32 +486,62 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
         for (int j = 0; j < 4; ++j) acc[ii][j] = M::mma(a[ii], bq[j], acc[ii][j]);
     }
   };
-  // one chunk: wait for its own loads (leave the next chunk's in flight),
-  // convert it in place, queue the chunk two ahead into the slot freed by the
-  // previous chunk, multiply
-  auto step = [&](int ch, uint16_t* cur, uint16_t* ahead) {
-    if (ch + 1 < c1) {
-      if (nld == 3) __builtin_amdgcn_s_waitcnt(0x0F70 | 3);
-      else if (nld == 2) __builtin_amdgcn_s_waitcnt(0x0F70 | 2);
-      else if (nld == 1) __builtin_amdgcn_s_waitcnt(0x0F70 | 1);
-      else __builtin_amdgcn_s_waitcnt(0x0F70);
-    } else {
-      __builtin_amdgcn_s_waitcnt(0x0F70);
-    }
+  // Each lane converts exactly the 16 bytes it loaded itself (same row and
+  // slot mapping in issue and convert), so converting a chunk needs only the
+  // wave's own load count, not a barrier.  One barrier per chunk: after it,
+  // every wave has converted chunk ch (the products may read any row) and
+  // finished multiplying chunk ch - 1 (its slot takes chunk ch + 2).  Then the
+  // wave queues ch + 2, multiplies ch and converts its own rows of ch + 1,
+  // whose loads were queued two products earlier; one wave's conversion
+  // overlaps the products of another on the same SIMD.
+  // Steady state: every step queues exactly S2IT loads, and waiting for the
+  // previous chunk leaves exactly those in flight.
+  static_assert(S2IT <= 15, "vmcnt immediate");
+  auto full = [&](int ch, uint16_t* cur, uint16_t* nxt, uint16_t* ahead) {
     lds_barrier();
-    convert(ch, cur);
+    issue(ch + 2, ahead);
+    multiply(cur);
+    __builtin_amdgcn_s_waitcnt(0x0F70 | S2IT);
+    convert(ch + 1, nxt);
+  };
+  // the last steps: nothing or only the final chunk left to queue
+  auto last = [&](int ch, uint16_t* cur, uint16_t* nxt, uint16_t* ahead) {
     lds_barrier();
     if (ch + 2 < c1) issue(ch + 2, ahead);
     multiply(cur);
+    if (ch + 2 < c1) {
+      __builtin_amdgcn_s_waitcnt(0x0F70 | S2IT);
+      convert(ch + 1, nxt);
+    } else if (ch + 1 < c1) {
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      convert(ch + 1, nxt);
+    }
   };
 
-  if (c0 < c1) issue(c0, ring0);
-  if (c0 + 1 < c1) issue(c0 + 1, ring1);
-  for (int ch = c0; ch < c1; ch += 3) {
-    step(ch, ring0, ring2);
-    if (ch + 1 < c1) step(ch + 1, ring1, ring0);
-    if (ch + 2 < c1) step(ch + 2, ring2, ring1);
+  // the shifts in shl are written by other threads than the ones reading
+  // them; publish them before the first conversion (nothing in flight yet)
+  __syncthreads();
+  if (c0 + 1 < c1) {
+    issue(c0, ring0);
+    issue(c0 + 1, ring1);
+    __builtin_amdgcn_s_waitcnt(0x0F70 | S2IT);
+    convert(c0, ring0);
+  } else if (c0 < c1) {
+    issue(c0, ring0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    convert(c0, ring0);
   }
+  int ch = c0;
+  for (; ch + 4 < c1; ch += 3) {
+    full(ch, ring0, ring1, ring2);
+    full(ch + 1, ring1, ring2, ring0);
+    full(ch + 2, ring2, ring0, ring1);
+  }
+  // at most four chunks remain, continuing the rotation at ring0
+  if (ch < c1) last(ch, ring0, ring1, ring2);
+  if (ch + 1 < c1) last(ch + 1, ring1, ring2, ring0);
+  if (ch + 2 < c1) last(ch + 2, ring2, ring0, ring1);
+  if (ch + 3 < c1) last(ch + 3, ring0, ring1, ring2);
 
   const int64_t slot = (int64_t)b * d.ks + split;
   using C = typename M::accs;
