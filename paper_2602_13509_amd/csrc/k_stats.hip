@@ -394,48 +394,59 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   // count or the row end load the line's first word (in bounds).  Rows below
   // the padded band count get zeros from the conversion; rows past it are
   // read only by products whose tiles are never stored.
+  // The descriptor fields live in registers for the whole loop, and chunk
+  // positions advance one chunk at a time (no division per chunk): a chunk
+  // is KC samples of one line, at sample s0 of the line starting at lb.
+  const int nB = d.B, nBp = d.Bp, nS = d.S;
+  const int64_t line_bytes = 2 * (int64_t)nB * nS;
+  struct Pos { const char* lb; int s0; };
+  auto advance = [&](Pos& p) {
+    p.s0 += KC;
+    if (p.s0 >= nS) { p.s0 = 0; p.lb += line_bytes; }
+  };
   const int segc = lslot ^ lrow;
-  const uint32_t loff = 2u * ((uint32_t)(8 * wv + lrow) * (uint32_t)d.S + 8u * (uint32_t)segc);
-  const uint32_t qstep = 2u * 128u * (uint32_t)d.S;
-  auto issue = [&](int ch, uint16_t* buf) {
-    const unsigned line = (unsigned)ch / (unsigned)d.cpl;
-    const int s0 = (int)((unsigned)ch - line * (unsigned)d.cpl) * KC;
-    const int nvalid = min(KC, d.S - s0);
-    const char* lb = reinterpret_cast<const char*>(xb + (int64_t)line * d.B * d.S + s0);
+  uint32_t offq[S2IT];                           // lane offsets of a whole chunk, per round
+#pragma unroll
+  for (int q = 0; q < S2IT; ++q)
+    offq[q] = (128 * q + 8 * wv + lrow < nB)
+                  ? 2u * ((uint32_t)(128 * q + 8 * wv + lrow) * (uint32_t)nS + 8u * (uint32_t)segc) : 0u;
+  auto issue = [&](const Pos& p, uint16_t* buf) {
+    const char* lb = p.lb + 2 * p.s0;
+    const bool ragged = nS - p.s0 < KC;          // wave-uniform
 #pragma unroll
     for (int q = 0; q < S2IT; ++q) {
-      const int r0 = 128 * q + 8 * wv;           // wave-uniform, < S3RING
-      const bool ok = (r0 + lrow < d.B) && (8 * segc < nvalid);
-      const uint32_t off = ok ? loff + (uint32_t)q * qstep : 0u;
+      uint32_t off = offq[q];
+      if (ragged) off = (8 * segc < nS - p.s0) ? off : 0u;
       __builtin_amdgcn_global_load_lds((const void*)(lb + off),
-                                       (__attribute__((address_space(3))) void*)(buf + r0 * KC), 16, 0, 0);
+                                       (__attribute__((address_space(3))) void*)(buf + (128 * q + 8 * wv) * KC),
+                                       16, 0, 0);
     }
   };
 
   uint32_t rawsum[S2IT];
 #pragma unroll
   for (int q = 0; q < S2IT; ++q) rawsum[q] = 0u;
-  for (int r = tid; r < d.Bp; r += S2NT) shl[r] = (r < d.B) ? (float)d.shift[(int64_t)b * d.Bp + r] : 0.0f;
-  // the direct path runs only when the sample count is a multiple of 8, so an
-  // 8-sample segment is either wholly inside the row or wholly past its end
+  for (int r = tid; r < nBp; r += S2NT) shl[r] = (r < nB) ? (float)d.shift[(int64_t)b * nBp + r] : 0.0f;
+  // The direct path runs only when the sample count is a multiple of 8, so an
+  // 8-sample segment is either wholly inside the row or wholly past its end.
   // Per 32-bit word (two samples): two conversions and two subtractions in
   // FP32 (exact for any 16-bit count), one packed rounding to the operand
-  // format, and the exact raw sum by a 16-bit dot product with (1, 1).  Rounds whose 8 rows all lie inside the band count,
-  // in chunks without a ragged end, need no masking (a wave-uniform test);
-  // elsewhere items outside become raw 0 with shift 0 and so convert to +0.
-  auto convert = [&](int ch, uint16_t* buf) {
-    const int s0 = (int)((unsigned)ch % (unsigned)d.cpl) * KC;
-    const int nvalid = min(KC, d.S - s0);
+  // format, and the exact raw sum by a 16-bit dot product with (1, 1).
+  // Rounds whose 8 rows all lie inside the band count, in chunks without a
+  // ragged end, need no masking (a wave-uniform test); elsewhere items
+  // outside become raw 0 with shift 0 and so convert to +0.
+  auto convert = [&](int s0, uint16_t* buf) {
+    const int nvalid = min(KC, nS - s0);
 #pragma unroll
     for (int q = 0; q < S2IT; ++q) {
       const int rb = 128 * q + 8 * wv;           // first row of the wave's round (uniform)
-      if (rb >= d.Bp) continue;
+      if (rb >= nBp) continue;
       const int r = rb + lrow;
       uint4* p = reinterpret_cast<uint4*>(buf + r * KC + 8 * lslot);
       uint4 wv4 = *p;
       float sh = shl[r];
-      if (!(rb + 8 <= d.B && nvalid == KC)) {
-        const bool ok = (r < d.B) && (8 * (lslot ^ lrow) < nvalid);
+      if (!(rb + 8 <= nB && nvalid == KC)) {
+        const bool ok = (r < nB) && (8 * segc < nvalid);
         wv4 = ok ? wv4 : uint4{0u, 0u, 0u, 0u};
         sh = ok ? sh : 0.0f;
       }
@@ -460,7 +471,7 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
     while (t > I) { t -= I + 1; ++I; }
     J = t;
   }
-  const int nsup = (d.Bp + 63) >> 6;
+  const int nsup = (nBp + 63) >> 6;
   const bool active = I < nsup;
   typename M::acc acc[4][4];
 #pragma unroll
@@ -497,24 +508,40 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   // Steady state: every step queues exactly S2IT loads, and waiting for the
   // previous chunk leaves exactly those in flight.
   static_assert(S2IT <= 15, "vmcnt immediate");
-  auto full = [&](int ch, uint16_t* cur, uint16_t* nxt, uint16_t* ahead) {
+  // ip: next chunk to queue; cs0: first sample of the next chunk to convert
+  Pos ip;
+  {
+    const int line = c0 / d.cpl;
+    ip = Pos{reinterpret_cast<const char*>(xb) + line * line_bytes, (c0 - line * d.cpl) * KC};
+  }
+  int cs0 = ip.s0;
+  auto conv_next = [&](uint16_t* buf) {
+    convert(cs0, buf);
+    cs0 += KC;
+    if (cs0 >= nS) cs0 = 0;
+  };
+  auto queue_next = [&](uint16_t* buf) {
+    issue(ip, buf);
+    advance(ip);
+  };
+  auto full = [&](uint16_t* cur, uint16_t* nxt, uint16_t* ahead) {
     lds_barrier();
-    issue(ch + 2, ahead);
+    queue_next(ahead);
     multiply(cur);
     __builtin_amdgcn_s_waitcnt(0x0F70 | S2IT);
-    convert(ch + 1, nxt);
+    conv_next(nxt);
   };
   // the last steps: nothing or only the final chunk left to queue
   auto last = [&](int ch, uint16_t* cur, uint16_t* nxt, uint16_t* ahead) {
     lds_barrier();
-    if (ch + 2 < c1) issue(ch + 2, ahead);
+    if (ch + 2 < c1) queue_next(ahead);
     multiply(cur);
     if (ch + 2 < c1) {
       __builtin_amdgcn_s_waitcnt(0x0F70 | S2IT);
-      convert(ch + 1, nxt);
+      conv_next(nxt);
     } else if (ch + 1 < c1) {
       __builtin_amdgcn_s_waitcnt(0x0F70);
-      convert(ch + 1, nxt);
+      conv_next(nxt);
     }
   };
 
@@ -522,20 +549,20 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   // them; publish them before the first conversion (nothing in flight yet)
   __syncthreads();
   if (c0 + 1 < c1) {
-    issue(c0, ring0);
-    issue(c0 + 1, ring1);
+    queue_next(ring0);
+    queue_next(ring1);
     __builtin_amdgcn_s_waitcnt(0x0F70 | S2IT);
-    convert(c0, ring0);
+    conv_next(ring0);
   } else if (c0 < c1) {
-    issue(c0, ring0);
+    queue_next(ring0);
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    convert(c0, ring0);
+    conv_next(ring0);
   }
   int ch = c0;
   for (; ch + 4 < c1; ch += 3) {
-    full(ch, ring0, ring1, ring2);
-    full(ch + 1, ring1, ring2, ring0);
-    full(ch + 2, ring2, ring0, ring1);
+    full(ring0, ring1, ring2);
+    full(ring1, ring2, ring0);
+    full(ring2, ring0, ring1);
   }
   // at most four chunks remain, continuing the rotation at ring0
   if (ch < c1) last(ch, ring0, ring1, ring2);
