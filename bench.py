@@ -64,6 +64,16 @@ def phase_work(B, px, esz, nblk):
     }
 
 
+def phase_cus(nblk, px, ncu):
+    """CUs a launch of each phase occupies (one workgroup per CU for the
+    covariance, whitening and factor kernels, whose LDS use allows one; the
+    merge kernels fill the GPU)."""
+    ks = -(-BLOCK * (-(-SAMPLES // 64)) // 91)
+    tiles = px // 64
+    return {"covariance": min(ncu, nblk * ks), "whiten_score": min(ncu - 32, max(1, tiles // 16)),
+            "factor": min(ncu, nblk), "merge": ncu}
+
+
 def roofline(kernel, w, ms):
     bound, fl, by, pk = w
     sec = ms * 1e-3
@@ -105,6 +115,9 @@ def measured_traffic(phase):
     return rec.get("bytes_per_launch")
 
 
+PROFILED_PUSHES = 5
+
+
 def run_path(rx, torch, x, prec, steps, warmup, label):
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
                          ridge_rel=RIDGE if prec != "fp64" else 0.0, block_lines=BLOCK, window_lines=LINES)
@@ -134,11 +147,13 @@ def run_path(rx, torch, x, prec, steps, warmup, label):
     st.rx_sync()
     t1 = time.perf_counter()
     # phase timings from a second, profiled pass (events around every phase
-    # add host work, so they stay out of the timed steps)
+    # add host work, so they stay out of the timed steps).  Each push runs to
+    # the end before the next starts, so every phase's events bracket its
+    # kernels alone, not time spent waiting for CUs held by the next push
     st.rx_profile(True)
-    for _ in range(max(3, steps // 4)):
+    for _ in range(PROFILED_PUSHES):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
     ms, n = st.rx_phase_times()
     st.rx_profile(False)
     first = sc.cpu().numpy().astype(np.float64)
@@ -313,10 +328,13 @@ def main():
         f"max rel {err.max():.3e}, p99 rel {np.quantile(err, 0.99):.3e}")
 
     # roofline of the dominant kernel of the mixed path: the phase with the
-    # longest launch, timed live with HIP events on the library's stream
+    # largest share of the step's CU-time (launch time, timed live with HIP
+    # events on the library's stream, times the CUs the launch occupies; the
+    # factorisation holds one CU per block beside the streaming kernels)
     work = phase_work(BANDS, npx, 2, LINES // BLOCK)
     per = {PHASES[i]: ms_mix[i] / max(n_mix[i], 1) for i in range(5)}
-    dom = max(work, key=lambda p: per[p])
+    cus = phase_cus(LINES // BLOCK, npx, torch.cuda.get_device_properties(0).multi_processor_count)
+    dom = max(work, key=lambda p: per[p] * cus[p])
     roof = roofline(dom, work[dom], per[dom])
     roof["traffic"] = measured_traffic(dom)
     phases = {}
