@@ -19,9 +19,13 @@ namespace rxk {
 constexpr int MAXBP = 16 * MAXT;
 constexpr int FNW = 8;                  // waves per factor workgroup (2 per SIMD: 256 registers each)
 constexpr int FNT = 64 * FNW;           // threads per factor workgroup
-// lower tiles per wave: a template argument sized to the band count; up to
-// 20 tiles (B <= 272) the tiles and the step's temporaries fit in registers
-constexpr int ftpw_for(int T) { return (T * (T + 1) / 2 + FNW - 1) / FNW; }
+// tiles per wave, a template argument sized to the band count: wave 0 holds
+// the T diagonal tiles, the other waves share the T (T - 1) / 2 tiles below
+// the diagonal; up to 20 tiles (B <= 272) they and the step's temporaries fit
+// in registers
+constexpr int ftpw_for(int T) {
+  return T > (T * (T - 1) / 2 + FNW - 2) / (FNW - 1) ? T : (T * (T - 1) / 2 + FNW - 2) / (FNW - 1);
+}
 constexpr int FTS = 16 * 17;            // LDS tile: 16 rows, pitch 17 doubles (bank-conflict free)
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
@@ -42,7 +46,7 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
   double* W = d.w64 + b * bp2;
   __shared__ double lcol[MAXT * FTS];   // pivot column: R_ik, then L_ik
   __shared__ double prow[MAXT * FTS];   // pivot row: E_kj, then W_kj; Y at k
-  __shared__ double ybuf[FTS];          // Y = L_kk^{-1}
+  __shared__ double ybuf[2][FTS];       // Y_k = L_kk^{-1}, by step parity
   __shared__ double sc[MAXBP];          // equilibration scale
   __shared__ double T22[16][17];
   __shared__ double red[FNW];
@@ -81,15 +85,20 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
     return;
   }
 
-  // ---- one right-looking sweep over 16x16 tiles held in registers:
-  // every lower tile (i, j) of R lives in one wave (cyclic ownership).  At
-  // step k the diagonal tile is factored (L_kk, Y = L_kk^{-1}); the pivot
-  // column becomes L_ik = R_ik Y^T; the pivot row of the eliminated identity
-  // becomes final rows of W = L^{-1}: W_kj = Y E_kj (W_kk = Y); every tile
-  // below row k is then updated with one 16x16x16 product:
-  //   j > k: R_ij -= L_ik L_jk^T     j == k: E_ik = -L_ik Y     j < k: E_ij -= L_ik W_kj
-  // so each tile holds R, then L (pivot column), then E, then W.
-  const int T = Bp / 16, ntiles = T * (T + 1) / 2;
+  // ---- one right-looking sweep over 16x16 tiles held in registers.  Wave 0
+  // owns the diagonal tiles (slot s holds tile (s, s)); the other waves own
+  // the tiles below the diagonal, cyclically in row-major order.  Step k, with
+  // Y_k = L_kk^{-1} already known:
+  //   P: the pivot column becomes L_ik = R_ik Y_k^T and the pivot row of the
+  //      eliminated identity becomes final rows of W = L^{-1}:
+  //      W_kj = Y_k E_kj, W_kk = Y_k; each owner forms its own tiles and
+  //      publishes them in LDS;
+  //   U: every tile below row k takes one 16x16x16 product:
+  //      j > k: R_ij -= L_ik L_jk^T   j == k: E_ik = -L_ik Y_k   j < k: E_ij -= L_ik W_kj
+  //      and wave 0, once its own updates are done, factors the new diagonal
+  //      tile (k + 1, k + 1) into Y_{k+1} while the other waves still update.
+  // Two barriers per step; each tile holds R, then L, then E, then W.
+  const int T = Bp / 16;
   const int lr = lane & 15, lg = lane >> 4;
   // LDS tiles are row-major with pitch 17: element (r, c) at r * 17 + c.
   // offA: this lane's element of an A-operand (or transposed B) read, (lr, 4q + lg);
@@ -101,11 +110,19 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
   int ti[FTPW], tj[FTPW];
 #pragma unroll
   for (int s = 0; s < FTPW; ++s) {
-    const int t = s * FNW + wv;
-    int i = 0;
-    while ((i + 1) * (i + 2) / 2 <= t) ++i;
-    ti[s] = __builtin_amdgcn_readfirstlane((t < ntiles) ? i : -1);
-    tj[s] = __builtin_amdgcn_readfirstlane((t < ntiles) ? t - i * (i + 1) / 2 : -1);
+    int i = -1, j = -1;
+    if (wv == 0) {
+      if (s < T) { i = s; j = s; }
+    } else {
+      const int u = s * (FNW - 1) + (wv - 1);      // index among the tiles below the diagonal
+      if (u < T * (T - 1) / 2) {
+        i = 1;
+        while ((i + 1) * i / 2 <= u) ++i;
+        j = u - i * (i - 1) / 2;
+      }
+    }
+    ti[s] = __builtin_amdgcn_readfirstlane(i);
+    tj[s] = __builtin_amdgcn_readfirstlane(j);
     tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
     if (ti[s] >= 0) {
 #pragma unroll
@@ -122,121 +139,139 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
     }
     if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // at most four tiles of loads in flight
   }
-  for (int k = 0; k < T; ++k) {
-    int offA = offA0, offB = offB0;
-    asm volatile("" : "+v"(offA), "+v"(offB));   // keep derived addresses inside the step
-    // stage the tiles this step reads from other waves
+
+  // 16x16 Cholesky of the diagonal tile staged in T22 and Y = L^{-1} together,
+  // in wave 0: lane = (row i, column group cg of 4) holds S[i][4cg..4cg+3] and
+  // the eliminated identity E[i][4cg..4cg+3].  Column j: pivot d = sqrt(S[j][j]),
+  // L[i][j] = S[i][j] / d, Y[j][.] = E[j][.] / d, then S[i][k] -= L[i][j] L[k][j]
+  // (j < k <= i) and E[i][.] -= L[i][j] Y[j][.] (i > j).
+  auto diag = [&](double* yout) {
+    int i = lane & 15, cg = lane >> 4;
+    asm volatile("" : "+v"(i), "+v"(cg));    // shuffle addresses are formed per step, not hoisted
+    double v[4], y[4];
 #pragma unroll
-    for (int s = 0; s < FTPW; ++s) {
-      double* dst = nullptr;
-      if (ti[s] == k && tj[s] == k) dst = &T22[0][0];
-      else if (tj[s] == k && ti[s] > k) dst = lcol + ti[s] * FTS;
-      else if (ti[s] == k && tj[s] >= 0 && tj[s] < k) dst = prow + tj[s] * FTS;
-      if (dst) {
-        double* p = dst + offB;
+    for (int e = 0; e < 4; ++e) {
+      v[e] = T22[i][4 * cg + e];
+      y[e] = (i == 4 * cg + e) ? 1.0 : 0.0;
+    }
+    bool bad = false;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+    for (int j = 0; j < 16; ++j) {
+      const int je = j & 3, jg = j >> 2;
+      const double piv = readlane_d(v[je], j + 16 * jg);
+      bad |= !(piv > 0.0);
+      const double rd = 1.0 / sqrt(piv);
+      const double lij = __shfl(v[je], i + 16 * jg, 64) * rd;
+      double lkj[4], yj[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
+        yj[e] = __shfl(y[e], j + 16 * cg, 64) * rd;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = 4 * cg + e;
+        if (kk > j && i >= kk) v[e] -= lij * lkj[e];
+        y[e] = (i == j) ? yj[e] : ((i > j) ? y[e] - lij * yj[e] : y[e]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
-    // 16x16 Cholesky of the diagonal tile and Y = L_kk^{-1} together, in wave 0:
-    // lane = (row i, column group cg of 4) holds S[i][4cg..4cg+3] and the
-    // eliminated identity E[i][4cg..4cg+3].  Column j: pivot d = sqrt(S[j][j]),
-    // L[i][j] = S[i][j] / d, Y[j][.] = E[j][.] / d, then S[i][k] -= L[i][j] L[k][j]
-    // (j < k <= i) and E[i][.] -= L[i][j] Y[j][.] (i > j).
-    if (wv == 0) {
-      int i = lane & 15, cg = lane >> 4;
-      asm volatile("" : "+v"(i), "+v"(cg));    // shuffle addresses are formed per step, not hoisted
-      double v[4], y[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        v[e] = T22[i][4 * cg + e];
-        y[e] = (i == 4 * cg + e) ? 1.0 : 0.0;
+    for (int e = 0; e < 4; ++e) yout[i * 17 + 4 * cg + e] = y[e];
+    if (lane == 0 && bad) flag = 1;
+  };
+  // wave 0 puts its diagonal tile kd into T22 (the same wave reads it back)
+  auto stage_diag = [&](int kd) {
+#pragma unroll
+    for (int s = 0; s < FTPW; ++s) {
+      if (ti[s] == kd && tj[s] == kd) {
+        double* p = &T22[0][0] + offB0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
       }
-      bool bad = false;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  };
+
+  // Step -1 only factors the first diagonal tile, so one copy of the
+  // diagonal code serves every step.
+  for (int k = -1; k < T && !flag; ++k) {
+    if (k >= 0) {
+      int offA = offA0, offB = offB0;
+      asm volatile("" : "+v"(offA), "+v"(offB));   // keep derived addresses inside the step
+      const double* yk = ybuf[k & 1];
+      // ---- P: pivot column L_ik = R_ik Y_k^T, pivot row W_kj = Y_k E_kj, W_kk = Y_k
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int je = j & 3, jg = j >> 2;
-        const double piv = readlane_d(v[je], j + 16 * jg);
-        bad |= !(piv > 0.0);
-        const double rd = 1.0 / sqrt(piv);
-        const double lij = __shfl(v[je], i + 16 * jg, 64) * rd;
-        double lkj[4], yj[4];
+      for (int s = 0; s < FTPW; ++s) {
+        if (tj[s] == k && ti[s] > k) {
+          // R_ik goes through this wave's LDS slot to be read in operand order
+          double* lc = lcol + ti[s] * FTS;
+          double* p = lc + offB;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
-          yj[e] = __shfl(y[e], j + 16 * cg, 64) * rd;
-        }
+          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          const double* la = lc + offA;
+          const double* yb = yk + offA;
+          tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int kk = 4 * cg + e;
-          if (kk > j && i >= kk) v[e] -= lij * lkj[e];
-          y[e] = (i == j) ? yj[e] : ((i > j) ? y[e] - lij * yj[e] : y[e]);
+          for (int q4 = 0; q4 < 4; ++q4)
+            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[4 * q4], yb[4 * q4], tl[s], 0, 0, 0);
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+        } else if (ti[s] == k && tj[s] >= 0 && tj[s] < k) {
+          // E_kj goes through this wave's LDS slot (each lane reads back the
+          // elements it wrote), then W_kj replaces it there
+          double* pr = prow + tj[s] * FTS;
+          double* p = pr + offB;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          const double* ya = yk + offA;
+          const double* pb = pr + offB;
+          tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4)
+            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
+        } else if (ti[s] == k && tj[s] == k) {
+          const double* yb = yk + offB;
+          double* p = prow + k * FTS + offB;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            tl[s][r] = yb[68 * r];
+            p[68 * r] = tl[s][r];
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
+      __syncthreads();
+      // ---- U: update every tile below row k
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ybuf[i * 17 + 4 * cg + e] = y[e];
-      if (lane == 0 && bad) flag = 1;
-    }
-    __syncthreads();
-    if (flag) break;
-    // pivot column L_ik = R_ik Y^T, pivot row W_kj = Y E_kj, W_kk = Y
+      for (int s = 0; s < FTPW; ++s) {
+        if (ti[s] > k) {
+          const double* la = lcol + ti[s] * FTS + offA;
+          if (tj[s] == k) tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+          if (tj[s] > k) {
+            const double* lb = lcol + tj[s] * FTS + offA;
 #pragma unroll
-    for (int s = 0; s < FTPW; ++s) {
-      if (tj[s] == k && ti[s] > k) {
-        double* lc = lcol + ti[s] * FTS;
-        const double* la = lc + offA;
-        const double* yb = ybuf + offA;
-        tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int q4 = 0; q4 < 4; ++q4)
+              tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], lb[4 * q4], tl[s], 0, 0, 0);
+          } else {
+            const double* pb = prow + tj[s] * FTS + offB;
 #pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
-          tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[4 * q4], yb[4 * q4], tl[s], 0, 0, 0);
-        double* p = lc + offB;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-      } else if (ti[s] == k && tj[s] >= 0 && tj[s] < k) {
-        double* pr = prow + tj[s] * FTS;
-        const double* ya = ybuf + offA;
-        const double* pb = pr + offB;
-        tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
-          tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
-        double* p = pr + offB;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-      } else if (ti[s] == k && tj[s] == k) {
-        const double* yb = ybuf + offB;
-        double* p = prow + k * FTS + offB;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          tl[s][r] = yb[68 * r];
-          p[68 * r] = tl[s][r];
+            for (int q4 = 0; q4 < 4; ++q4)
+              tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
+          }
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
-    // update every tile below row k
-#pragma unroll
-    for (int s = 0; s < FTPW; ++s) {
-      if (ti[s] > k) {
-        const double* la = lcol + ti[s] * FTS + offA;
-        if (tj[s] == k) tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-        if (tj[s] > k) {
-          const double* lb = lcol + tj[s] * FTS + offA;
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4)
-            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], lb[4 * q4], tl[s], 0, 0, 0);
-        } else {
-          const double* pb = prow + tj[s] * FTS + offB;
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4)
-            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
-        }
-      }
+    // wave 0: the next diagonal tile is final now; factor it
+    if (wv == 0 && k + 1 < T) {
+      stage_diag(k + 1);
+      diag(ybuf[(k + 1) & 1]);
     }
     __syncthreads();
   }
