@@ -143,6 +143,42 @@ rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_wr
 rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits,
                   int64_t max_bytes, int64_t* n_px, int32_t out_is_device, void* hip_stream);
 
+/* ---------------------------------------------------------------- transmission
+ * The sender's score encoding and the receiver's inverse (paper, Section
+ * "System Implementation / Data Transmission" and "... / Ground Control
+ * Station"; the 0.110 threshold of Section "Results / Detector Visual
+ * Analysis").  Sender: s_p = sqrt(delta_p) in FP32, m = the largest s_p (so
+ * m = sqrt(max delta); NaN scores are skipped, m = 0 when none is finite),
+ * code_p = binary16(s_p / m) rounded to nearest even: the cube's highest
+ * score codes as 1.0; with m = 0 finite scores code as 0; NaN scores code
+ * as a binary16 NaN.  Scores are expected to be >= 0 (a negative one codes
+ * as NaN).  Receiver: h_p = the binary16 value, delta^_p = (h_p m)^2 in FP32
+ * (the normalisation undone, then squared), and the relative threshold bit
+ * h_p^2 > tau (h_p^2 is exact in FP32).
+ *
+ * rx_tx_encode: scores [n] FP32, codes [n] (binary16 bit patterns) and
+ * max_out (one FP32, 4-byte aligned) are device pointers on the current
+ * device; the work is queued on hip_stream (NULL: the null stream).  max_out
+ * holds an intermediate key while the call's work runs and m once it is done.
+ * rx_tx_decode: codes [n] and max_in (m, as written by rx_tx_encode) are
+ * device pointers; delta [n] (FP32) and bits (ceil(n/32) 32-bit words,
+ * 4-byte aligned; bit j of byte q is pixel 8q + j, as in rx_mask) are
+ * device pointers or NULL to skip that output.  Both return RX_E_ARG for
+ * n < 0, a NaN tau, or a missing or misaligned pointer; nothing is written
+ * then. */
+rx_status rx_tx_encode(const float* scores, int64_t n, uint16_t* codes, float* max_out, void* hip_stream);
+rx_status rx_tx_decode(const uint16_t* codes, int64_t n, const float* max_in, float tau, float* delta,
+                       uint32_t* bits, void* hip_stream);
+
+/* rx_tx_encode over the stream's pending scores, without consuming them
+ * (the transmitted set of the paper's cube is the pending set, as for
+ * rx_mask).  codes (at least the pending count) and max_out are device
+ * pointers on the stream's device; the result is ordered before later work
+ * on hip_stream.  *n_px = pending pixels encoded.  FP64 scores of the plain
+ * FP64 path are rounded to FP32 first. */
+rx_status rx_encode(rx_stream* s, uint16_t* codes, int64_t max_px, int64_t* n_px, float* max_out,
+                    void* hip_stream);
+
 /* Make hip_stream wait for every block pushed so far (no host block). */
 rx_status rx_wait(rx_stream* s, void* hip_stream);
 

@@ -32,6 +32,10 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const LaunchSet*
                                         hipStream_t st);
 extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mode, double tau, int64_t k,
                                       uint32_t* bits, void* scratch, hipStream_t st);
+extern "C" hipError_t rxk_launch_tx_encode(const void* sc, int f64, int64_t n, uint16_t* codes, float* mslot,
+                                           hipStream_t st);
+extern "C" hipError_t rxk_launch_tx_decode(const uint16_t* codes, int64_t n, const float* mslot, float tau,
+                                           float* delta, uint32_t* bits, hipStream_t st);
 
 static_assert(sizeof(LaunchSet) < 4000, "kernel-argument descriptor set too large");
 
@@ -863,6 +867,45 @@ extern "C" rx_status rx_scores(rx_stream* s, float* out, int64_t max_px, int64_t
 extern "C" rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_written,
                                    int32_t out_is_device, void* hip_stream) {
   return pop_scores(s, out, 1, max_px, n_written, out_is_device, hip_stream);
+}
+
+// ---------------------------------------------------------------------------- transmission encoding
+static bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+extern "C" rx_status rx_tx_encode(const float* scores, int64_t n, uint16_t* codes, float* max_out, void* hip_stream) {
+  if (n < 0) return fail(RX_E_ARG, "n must be >= 0");
+  if (!max_out || !aligned4(max_out)) return fail(RX_E_ARG, "max_out must be a 4-byte aligned device pointer");
+  if (n > 0 && (!scores || !codes)) return fail(RX_E_ARG, "null scores or codes");
+  HIPC(rxk_launch_tx_encode(scores, 0, n, codes, max_out, static_cast<hipStream_t>(hip_stream)));
+  return RX_OK;
+}
+
+extern "C" rx_status rx_tx_decode(const uint16_t* codes, int64_t n, const float* max_in, float tau, float* delta,
+                                  uint32_t* bits, void* hip_stream) {
+  if (n < 0) return fail(RX_E_ARG, "n must be >= 0");
+  if (std::isnan(tau)) return fail(RX_E_ARG, "tau is NaN");
+  if (!max_in || !aligned4(max_in)) return fail(RX_E_ARG, "max_in must be a 4-byte aligned device pointer");
+  if (n > 0 && !codes) return fail(RX_E_ARG, "null codes");
+  if (bits && !aligned4(bits)) return fail(RX_E_ARG, "bits must be 4-byte aligned");
+  HIPC(rxk_launch_tx_decode(codes, n, max_in, tau, delta, bits, static_cast<hipStream_t>(hip_stream)));
+  return RX_OK;
+}
+
+extern "C" rx_status rx_encode(rx_stream* s, uint16_t* codes, int64_t max_px, int64_t* n_px, float* max_out,
+                               void* hip_stream) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!n_px) return fail(RX_E_ARG, "null n_px");
+  if (!max_out || !aligned4(max_out)) return fail(RX_E_ARG, "max_out must be a 4-byte aligned device pointer");
+  HIPC(hipSetDevice(s->dev));
+  const int64_t n = s->tail - s->head;
+  *n_px = n;
+  if (n > 0 && (!codes || max_px < n)) return fail(RX_E_ARG, "codes buffer needs %lld entries", (long long)n);
+  const void* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * (s->sc_f64 ? 8 : 4);
+  HIPC(rxk_launch_tx_encode(src, s->sc_f64, n, codes, max_out, s->st));
+  HIPC(hipEventRecord(s->ev_done, s->st));
+  HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
+  return RX_OK;
 }
 
 extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits, int64_t max_bytes,

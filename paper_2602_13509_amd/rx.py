@@ -32,7 +32,7 @@ EXPORTED = [
     "rx_sync", "rx_get_counters", "rx_destroy", "rx_last_error", "rx_get_stats", "rx_set_stats",
     "rx_get_whitener", "rx_server_create", "rx_server_destroy", "rx_stream_footprint", "rx_server_submit",
     "rx_server_step", "rx_server_poll", "rx_server_sync", "rx_server_queued", "rx_profile",
-    "rx_phase_times",
+    "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode",
 ]
 
 
@@ -87,6 +87,9 @@ def _load():
         "rx_server_queued": (I32, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(SZ)]),
         "rx_profile": (I32, [P, I32]),
         "rx_phase_times": (I32, [P, P, P]),
+        "rx_tx_encode": (I32, [P, I64, P, P, P]),
+        "rx_tx_decode": (I32, [P, I64, P, C.c_float, P, P, P]),
+        "rx_encode": (I32, [P, P, I64, C.POINTER(I64), P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -186,6 +189,13 @@ class RxStream:
         size = out.numel() if hasattr(out, "numel") else out.size
         check(LIB.rx_mask(self.h, float(tau), mode, int(k), _ptr(out), size, C.byref(n), dev,
                           _stream_handle(stream) if dev else 0))
+        return n.value
+
+    def rx_encode(self, codes, max_out, stream=None) -> int:
+        """Transmission codes of the pending scores (codes: int16/uint16
+        device tensor, max_out: one-element float32 device tensor)."""
+        n = C.c_int64()
+        check(LIB.rx_encode(self.h, _ptr(codes), codes.numel(), C.byref(n), _ptr(max_out), _stream_handle(stream)))
         return n.value
 
     def rx_wait(self, stream=None):
@@ -294,3 +304,17 @@ def stream_footprint(cfg: rx_config, max_block_lines: int) -> int:
     b = C.c_size_t()
     check(LIB.rx_stream_footprint(C.byref(cfg), int(max_block_lines), C.byref(b)))
     return b.value
+
+
+def tx_encode(scores, codes, max_out, stream=None) -> None:
+    """rx_tx_encode on device tensors: scores float32 [n], codes int16/uint16
+    [n] (binary16 bit patterns), max_out float32 [1]."""
+    check(LIB.rx_tx_encode(_ptr(scores), scores.numel(), _ptr(codes), _ptr(max_out), _stream_handle(stream)))
+
+
+def tx_decode(codes, max_in, tau: float, delta=None, bits=None, stream=None) -> None:
+    """rx_tx_decode on device tensors: delta float32 [n] and bits int32
+    [ceil(n/32)] are optional outputs."""
+    check(LIB.rx_tx_decode(_ptr(codes), codes.numel(), _ptr(max_in), float(tau),
+                           _ptr(delta) if delta is not None else None,
+                           _ptr(bits) if bits is not None else None, _stream_handle(stream)))

@@ -224,3 +224,20 @@ def random_int_cube(seed: int, lines: int, samples: int, bands: int, hi: int = 1
     """Small BIL cube of uniform integers in [0, hi) (uint16), for exact tests."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, hi, size=(lines, bands, samples)).astype(np.uint16)
+
+
+def score_sample(seed: int, n: int, bands: int = 270, nan_frac: float = 0.0) -> np.ndarray:
+    """Seeded FP32 stand-ins for a cube's anomaly scores, for the transmission
+    stage: chi-square-like background draws (gamma with shape bands/2, scale
+    2), one in two thousand pixels a hundred times larger, exact zeros at a
+    few places, and optionally NaN at a fraction nan_frac (a singular block's
+    pixels).  Random numbers only; no part of the detector."""
+    rng = np.random.default_rng(seed)
+    d = rng.gamma(bands / 2.0, 2.0, size=n)
+    hot = rng.random(n) < 5e-4
+    d[hot] *= 100.0
+    if n:
+        d[rng.integers(0, n, size=max(1, n // 10000))] = 0.0
+    if nan_frac > 0:
+        d[rng.random(n) < nan_frac] = np.nan
+    return d.astype(np.float32)
