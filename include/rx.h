@@ -143,6 +143,21 @@ rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_wr
 rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits,
                   int64_t max_bytes, int64_t* n_px, int32_t out_is_device, void* hip_stream);
 
+/* ---------------------------------------------------------------- ingest binning
+ * Band selection and spectral binning of 16-bit counts (paper, Section
+ * "System Implementation / Data Acquisition": out-of-range bands discarded,
+ * 300 -> 280, then four consecutive bands summed into one, 280 -> 70).  For a
+ * BIL cube in [lines][bands][samples]:
+ *   out[l][j][s] = sum over t < k of in[l][b0 + j k + t][s],  j < nb / k,
+ * exact integer sums written as uint16 to out [lines][nb / k][samples].
+ * in and out are device pointers on the current device (not overlapping);
+ * the work is queued on hip_stream.  RX_E_ARG unless 1 <= k <= nb,
+ * nb % k == 0, 0 <= b0, b0 + nb <= bands, 1 <= bit_depth <= 16 and
+ * k (2^bit_depth - 1) <= 65535 (so no sum can overflow); nothing is written
+ * then.  The binned cube is then pushed like any other (bands = nb / k). */
+rx_status rx_bin_bands(const uint16_t* in, int64_t lines, int32_t bands, int32_t samples, int32_t b0,
+                       int32_t nb, int32_t k, int32_t bit_depth, uint16_t* out, void* hip_stream);
+
 /* ---------------------------------------------------------------- transmission
  * The sender's score encoding and the receiver's inverse (paper, Section
  * "System Implementation / Data Transmission" and "... / Ground Control

@@ -34,6 +34,8 @@ extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mo
                                       uint32_t* bits, void* scratch, hipStream_t st);
 extern "C" hipError_t rxk_launch_tx_encode(const void* sc, int f64, int64_t n, uint16_t* codes, float* mslot,
                                            hipStream_t st);
+extern "C" hipError_t rxk_launch_bin(const uint16_t* in, uint16_t* out, int64_t lines, int bands, int samples, int b0,
+                                     int nbo, int k, hipStream_t st);
 extern "C" hipError_t rxk_launch_tx_decode(const uint16_t* codes, int64_t n, const float* mslot, float tau,
                                            float* delta, uint32_t* bits, hipStream_t st);
 
@@ -867,6 +869,20 @@ extern "C" rx_status rx_scores(rx_stream* s, float* out, int64_t max_px, int64_t
 extern "C" rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_written,
                                    int32_t out_is_device, void* hip_stream) {
   return pop_scores(s, out, 1, max_px, n_written, out_is_device, hip_stream);
+}
+
+// ---------------------------------------------------------------------------- band selection and binning
+extern "C" rx_status rx_bin_bands(const uint16_t* in, int64_t lines, int32_t bands, int32_t samples, int32_t b0,
+                                  int32_t nb, int32_t k, int32_t bit_depth, uint16_t* out, void* hip_stream) {
+  if (lines < 0 || bands < 1 || samples < 1) return fail(RX_E_ARG, "bad cube shape");
+  if (k < 1 || nb < k || nb % k != 0) return fail(RX_E_ARG, "nb must be a positive multiple of k >= 1");
+  if (b0 < 0 || (int64_t)b0 + nb > bands) return fail(RX_E_ARG, "bands [b0, b0 + nb) outside [0, bands)");
+  if (bit_depth < 1 || bit_depth > 16) return fail(RX_E_ARG, "bit_depth must be in 1..16");
+  if ((int64_t)k * ((1ll << bit_depth) - 1) > 65535)
+    return fail(RX_E_ARG, "sums of %d counts of %d bits can exceed 16 bits", k, bit_depth);
+  if (lines > 0 && (!in || !out)) return fail(RX_E_ARG, "null input or output");
+  HIPC(rxk_launch_bin(in, out, lines, bands, samples, b0, nb / k, k, static_cast<hipStream_t>(hip_stream)));
+  return RX_OK;
 }
 
 // ---------------------------------------------------------------------------- transmission encoding

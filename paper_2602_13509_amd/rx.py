@@ -32,7 +32,7 @@ EXPORTED = [
     "rx_sync", "rx_get_counters", "rx_destroy", "rx_last_error", "rx_get_stats", "rx_set_stats",
     "rx_get_whitener", "rx_server_create", "rx_server_destroy", "rx_stream_footprint", "rx_server_submit",
     "rx_server_step", "rx_server_poll", "rx_server_sync", "rx_server_queued", "rx_profile",
-    "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode",
+    "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode", "rx_bin_bands",
 ]
 
 
@@ -90,6 +90,7 @@ def _load():
         "rx_tx_encode": (I32, [P, I64, P, P, P]),
         "rx_tx_decode": (I32, [P, I64, P, C.c_float, P, P, P]),
         "rx_encode": (I32, [P, P, I64, C.POINTER(I64), P, P]),
+        "rx_bin_bands": (I32, [P, I64, I32, I32, I32, I32, I32, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -318,3 +319,11 @@ def tx_decode(codes, max_in, tau: float, delta=None, bits=None, stream=None) -> 
     check(LIB.rx_tx_decode(_ptr(codes), codes.numel(), _ptr(max_in), float(tau),
                            _ptr(delta) if delta is not None else None,
                            _ptr(bits) if bits is not None else None, _stream_handle(stream)))
+
+
+def bin_bands(cube, b0: int, nb: int, k: int, out, bit_depth: int = 12, stream=None) -> None:
+    """rx_bin_bands on device tensors: cube uint16-valued [lines][bands][samples]
+    (torch int16 or uint16), out [lines][nb / k][samples] of the same dtype."""
+    lines, bands, samples = cube.shape
+    check(LIB.rx_bin_bands(_ptr(cube), lines, bands, samples, b0, nb, k, bit_depth, _ptr(out),
+                           _stream_handle(stream)))

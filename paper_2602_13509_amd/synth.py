@@ -241,3 +241,11 @@ def score_sample(seed: int, n: int, bands: int = 270, nan_frac: float = 0.0) -> 
     if nan_frac > 0:
         d[rng.random(n) < nan_frac] = np.nan
     return d.astype(np.float32)
+
+
+def raw_counts(seed: int, lines: int, bands: int, samples: int, bits: int = 12) -> np.ndarray:
+    """Seeded uniform raw counts of a bits-bit sensor as uint16 BIL
+    [lines][bands][samples] (the imager's raw 12-bit data, Section "System
+    Implementation / Data Acquisition"), for the ingest binning."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << bits, size=(lines, bands, samples), dtype=np.uint16)
