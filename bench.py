@@ -163,6 +163,79 @@ def run_path(rx, torch, x, prec, steps, warmup, label):
     return (t1 - t0) / steps, ms, n, first
 
 
+def transmit(rx, torch, npx, reps=20):
+    """Transmission stage over one cube's worth of scores (seeded score
+    sample of npx pixels): encode (maximum pass + code pass) and decode
+    (scores and threshold bits), timed with events on the stream the
+    kernels run on.  Algorithmic bytes per pixel: encode reads 4 and writes
+    2; decode reads 2 and writes 4 + 1/8."""
+    from paper_2602_13509_amd import synth
+    d = torch.from_numpy(synth.score_sample(0, npx)).cuda()
+    codes = torch.empty(npx, dtype=torch.int16, device="cuda")
+    mslot = torch.empty(1, dtype=torch.float32, device="cuda")
+    delta = torch.empty(npx, dtype=torch.float32, device="cuda")
+    words = torch.empty((npx + 31) // 32, dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        rx.tx_encode(d, codes, mslot)
+        rx.tx_decode(codes, mslot, 0.110, delta, words)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        rx.tx_encode(d, codes, mslot)
+    ev[1].record()
+    for _ in range(reps):
+        rx.tx_decode(codes, mslot, 0.110, delta, words)
+    ev[2].record()
+    torch.cuda.synchronize()
+    enc = ev[0].elapsed_time(ev[1]) / reps
+    dec = ev[1].elapsed_time(ev[2]) / reps
+    return {"px": npx, "encode_ms": enc, "decode_ms": dec,
+            "encode_GBps": npx * 6 / (enc * 1e-3) / 1e9, "decode_GBps": npx * (6 + 0.125) / (dec * 1e-3) / 1e9}
+
+
+PAPER_CUBE_S = 1.78      # the paper's detect step per 1000-line cube, one SBC core (Section "Results / Performance")
+
+
+def paper_workload(rx, torch, reps=5):
+    """The paper's own detector workload: cubes of 1000 lines x 900 samples x
+    300 bands of 12-bit counts; bands 10..289 kept and summed by four (70
+    bands); global RX per cube (statistics over the cube, then its scores:
+    one block, the window restarting every 1000 lines); scores encoded for
+    transmission.  Each cube runs to the end before the next (wall time per
+    cube, median of reps)."""
+    from paper_2602_13509_amd import synth
+    L, S, B = 1000, 900, 300
+    raw = torch.from_numpy(synth.sensor_cube(0, lines=L, samples=S, bands=B).cube).cuda()
+    binned = torch.empty((L, 70, S), dtype=torch.uint16, device="cuda")
+    codes = torch.empty(L * S, dtype=torch.int16, device="cuda")
+    mslot = torch.empty(1, dtype=torch.float32, device="cuda")
+    out = {}
+    for prec in ("bf16", "fp32"):
+        cfg = rx.make_config(70, S, in_dtype=np.uint16, syrk=prec, whiten=prec,
+                             ridge_rel=RIDGE if prec == "bf16" else 0.0, block_lines=L, window_lines=L, bit_depth=14)
+        st = rx.RxStream(cfg)
+        times = []
+        for it in range(reps + 2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rx.bin_bands(raw, 10, 280, 4, binned)
+            st.rx_push_lines(binned)
+            st.rx_encode(codes, mslot)
+            torch.cuda.synchronize()
+            st.rx_sync()
+            t1 = time.perf_counter()
+            n = st.pending()
+            st.rx_scores(torch.empty(n, dtype=torch.float32, device="cuda"))
+            if it >= 2:
+                times.append(t1 - t0)
+        st.rx_destroy()
+        med = float(np.median(times))
+        out[prec] = {"s_per_cube": med, "px_per_s": L * S / med, "vs_paper_cube_time": PAPER_CUBE_S / med}
+    return {"workload": "1000 x 900 x 300 12-bit cube, bands 10..289 summed by 4 -> 70, RX per cube, "
+                        "transmission codes", "paper_s_per_cube": PAPER_CUBE_S, **out}
+
+
 def latency(rx, torch, x, prec, nblocks):
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
                          ridge_rel=RIDGE, block_lines=0, window_lines=LINES)
@@ -301,6 +374,12 @@ def main():
         t_64, ms_64, n_64, _ = run_path(rx, torch, x, "fp64", k64, 1, "fp64")
     p50, p99 = latency(rx, torch, x, "bf16", 40)
     log(f"block latency (100 lines): p50 {p50:.3f} ms, p99 {p99:.3f} ms")
+    tx = transmit(rx, torch, npx)
+    pw = paper_workload(rx, torch)
+    log(f"paper workload (per cube): mixed {pw['bf16']['s_per_cube'] * 1e3:.3f} ms, "
+        f"fp32 {pw['fp32']['s_per_cube'] * 1e3:.3f} ms (paper: {PAPER_CUBE_S} s on one SBC core)")
+    log(f"transmission stage ({npx} px): encode {tx['encode_ms']:.4f} ms ({tx['encode_GBps']:.0f} GB/s), "
+        f"decode {tx['decode_ms']:.4f} ms ({tx['decode_GBps']:.0f} GB/s)")
 
     served = None
     if args.serve_seconds > 0:
@@ -361,6 +440,8 @@ def main():
         "score_error_vs_oracle": {"max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
                                   "pixels": int(nref)},
         "serving": served,
+        "transmit": tx,
+        "paper_workload": pw,
         "roofline": roof,
         "phases": phases,
         "cpu_baseline": cpu,
