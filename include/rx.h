@@ -124,7 +124,9 @@ rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_lines, int32_
 /* Pop up to max_px of the oldest pending scores (FP32) into out.
  * out_is_device = 0: host buffer, the call blocks until they are written.
  * out_is_device = 1: device buffer on cfg->device, written asynchronously
- * and ordered before later work on hip_stream.  *n_written = count popped. */
+ * after the work already queued on hip_stream (which may still be using the
+ * buffer) and ordered before later work on hip_stream.  *n_written = count
+ * popped. */
 rx_status rx_scores(rx_stream* s, float* out, int64_t max_px, int64_t* n_written,
                     int32_t out_is_device, void* hip_stream);
 
@@ -188,8 +190,8 @@ rx_status rx_tx_decode(const uint16_t* codes, int64_t n, const float* max_in, fl
 /* rx_tx_encode over the stream's pending scores, without consuming them
  * (the transmitted set of the paper's cube is the pending set, as for
  * rx_mask).  codes (at least the pending count) and max_out are device
- * pointers on the stream's device; the result is ordered before later work
- * on hip_stream.  *n_px = pending pixels encoded.  FP64 scores of the plain
+ * pointers on the stream's device; they are written after the work already
+ * queued on hip_stream and before later work on it.  *n_px = pending pixels encoded.  FP64 scores of the plain
  * FP64 path are rounded to FP32 first. */
 rx_status rx_encode(rx_stream* s, uint16_t* codes, int64_t max_px, int64_t* n_px, float* max_out,
                     void* hip_stream);

@@ -829,6 +829,15 @@ __global__ void k_f32_to_f64(const float* a, double* b, int64_t n) {
   if (i < n) b[i] = (double)a[i];
 }
 
+// A device output of the caller's may still be in use by earlier work on the
+// caller's stream (a fill, a reader, torch recycling the memory): the
+// library's queue waits for that work before writing it.
+static rx_status after_caller(rx_stream* s, void* hip_stream) {
+  HIPC(hipEventRecord(s->ev_in, static_cast<hipStream_t>(hip_stream)));
+  HIPC(hipStreamWaitEvent(s->st, s->ev_in, 0));
+  return RX_OK;
+}
+
 static rx_status pop_scores(rx_stream* s, void* out, int want_f64, int64_t max_px, int64_t* n_written,
                             int32_t out_is_device, void* hip_stream) {
   rx_status r = check_stream(s);
@@ -850,6 +859,7 @@ static rx_status pop_scores(rx_stream* s, void* out, int want_f64, int64_t max_p
     from = s->cvt.p;
   }
   if (out_is_device) {
+    if ((r = after_caller(s, hip_stream)) != RX_OK) return r;
     HIPC(hipMemcpyAsync(out, from, (size_t)n * eo, hipMemcpyDeviceToDevice, s->st));
     HIPC(hipEventRecord(s->ev_done, s->st));
     HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
@@ -918,6 +928,7 @@ extern "C" rx_status rx_encode(rx_stream* s, uint16_t* codes, int64_t max_px, in
   *n_px = n;
   if (n > 0 && (!codes || max_px < n)) return fail(RX_E_ARG, "codes buffer needs %lld entries", (long long)n);
   const void* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * (s->sc_f64 ? 8 : 4);
+  if ((r = after_caller(s, hip_stream)) != RX_OK) return r;
   HIPC(rxk_launch_tx_encode(src, s->sc_f64, n, codes, max_out, s->st));
   HIPC(hipEventRecord(s->ev_done, s->st));
   HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
@@ -948,6 +959,7 @@ extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, 
     HIPC(rxk_launch_mask(src, s->sc_f64, n, mode, tau, k, static_cast<uint32_t*>(s->maskbits.p), s->maskscr.p, s->st));
   }
   if (out_is_device) {
+    if ((r = after_caller(s, hip_stream)) != RX_OK) return r;
     HIPC(hipMemcpyAsync(bits, s->maskbits.p, (size_t)nbytes, hipMemcpyDeviceToDevice, s->st));
     HIPC(hipEventRecord(s->ev_done, s->st));
     HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
