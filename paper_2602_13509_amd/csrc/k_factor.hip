@@ -160,7 +160,16 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
       const int je = j & 3, jg = j >> 2;
       const double piv = readlane_d(v[je], j + 16 * jg);
       bad |= !(piv > 0.0);
-      const double rd = 1.0 / sqrt(piv);
+      // 1/sqrt(piv): the hardware reciprocal square root, then two Newton
+      // steps (each squares the relative error), within a few ulp of the
+      // correctly rounded value and far shorter than a square root and a
+      // division on this column's critical path
+      double rd = __builtin_amdgcn_rsq(piv);
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const double e = __builtin_fma(-piv * rd, rd, 1.0);
+        rd = __builtin_fma(0.5 * rd, e, rd);
+      }
       const double lij = __shfl(v[je], i + 16 * jg, 64) * rd;
       double lkj[4], yj[4];
 #pragma unroll
