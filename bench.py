@@ -120,7 +120,8 @@ PROFILED_PUSHES = 5
 
 def run_path(rx, torch, x, prec, steps, warmup, label):
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
-                         ridge_rel=RIDGE if prec != "fp64" else 0.0, block_lines=BLOCK, window_lines=LINES)
+                         ridge_rel=RIDGE if prec in ("bf16", "fp16", "fp8") else 0.0, block_lines=BLOCK,
+                         window_lines=LINES)
     st = rx.RxStream(cfg)
     npx = LINES * SAMPLES
     sc = torch.empty(npx, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
@@ -370,8 +371,10 @@ def main():
     k64 = max(2, args.steps // 5)
     if args.skip_fp64:
         t_64, ms_64, n_64 = float("nan"), [0.0] * 5, [0] * 5
+        t_32 = float("nan")
     else:
         t_64, ms_64, n_64, _ = run_path(rx, torch, x, "fp64", k64, 1, "fp64")
+        t_32, _, _, _ = run_path(rx, torch, x, "fp32", k64, 1, "fp32")
     p50, p99 = latency(rx, torch, x, "bf16", 40)
     log(f"block latency (100 lines): p50 {p50:.3f} ms, p99 {p99:.3f} ms")
     tx = transmit(rx, torch, npx)
@@ -436,6 +439,7 @@ def main():
                    "lines": LINES, "samples": SAMPLES, "bands": BANDS, "block_lines": BLOCK},
         "fp64_path": None if args.skip_fp64 else {"value": npx / t_64, "ms_per_step": t_64 * 1e3, "steps": k64},
         "mixed_over_fp64": None if args.skip_fp64 else t_64 / t_mix,
+        "fp32_path": None if args.skip_fp64 else {"value": npx / t_32, "ms_per_step": t_32 * 1e3, "steps": k64},
         "latency_ms": {"block_lines": BLOCK, "p50": p50, "p99": p99},
         "score_error_vs_oracle": {"max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
                                   "pixels": int(nref)},
