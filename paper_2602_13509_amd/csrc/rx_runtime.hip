@@ -194,6 +194,10 @@ struct rx_stream {
   bool own_st = false;
   hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr, ev_hcopy = nullptr;
   hipEvent_t ev_fact = nullptr, ev_merged[2] = {nullptr, nullptr}, ev_white[2] = {nullptr, nullptr};
+  // end of the latest push (recorded on st): a push finding it complete runs
+  // on st alone; after such a push, the next pipelined one makes stA wait for it
+  hipEvent_t ev_last = nullptr;
+  bool st_only_tail = false;
   int npar = 1, par = 0, last_par = 0;    // parity sets of the per-batch buffers (queued batches alternate)
   rx_server* srv = nullptr;
   size_t footprint = 0;
@@ -337,7 +341,7 @@ static void free_stream(rx_stream* s) {
   s->prof_pool.clear();
   s->prof_open.clear();
   hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_merged[0], s->ev_merged[1],
-                      s->ev_fact, s->ev_white[0], s->ev_white[1]};
+                      s->ev_fact, s->ev_white[0], s->ev_white[1], s->ev_last};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
   if (s->own_st) {
@@ -440,7 +444,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
     s->npar = 2;
   }
   hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_merged[0],
-                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1]};
+                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last};
   for (hipEvent_t* e : evs)
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
   const size_t s1b = (size_t)s->Bp * 8, m2b = (size_t)s->Bp * s->Bp * 8;
@@ -793,14 +797,29 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
   HIPC(hipSetDevice(s->dev));
   const size_t bytes = (size_t)n_lines * s->B * s->S * s->esz;
   const void* x = lines;
+  std::vector<Block> blks;
+  cut_blocks(s, s->lines_seen, n_lines, blks);
+  // A one-block device push to an idle stream (every earlier push done) runs
+  // on one queue: no cross-queue handoffs, the lowest latency for a lone
+  // block.  Other pushes go over the three queues, so that consecutive
+  // pushes overlap (a multi-block push's factorisation and whitening run
+  // beside the next push's covariance).  After a one-queue push, queue A
+  // first waits for it: its shift and covariance reuse the scratch that push
+  // read on queue C.
+  bool one_queue = false;
+  if (is_device_ptr && blks.size() == 1) {
+    const hipError_t q = hipEventQuery(s->ev_last);
+    if (q != hipSuccess && q != hipErrorNotReady) return fail(RX_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
+    one_queue = q == hipSuccess;
+  }
+  const Queues qs = one_queue ? Queues{s->st, s->st, s->st} : Queues{s->stA, s->stB, s->st};
+  if (!one_queue && s->st_only_tail) HIPC(hipStreamWaitEvent(s->stA, s->ev_last, 0));
   if (!is_device_ptr) {
     if ((r = stage_host_input(s, lines, bytes, &x)) != RX_OK) return r;
   } else {
     HIPC(hipEventRecord(s->ev_in, static_cast<hipStream_t>(hip_stream)));
-    HIPC(hipStreamWaitEvent(s->stA, s->ev_in, 0));   // queues B and C follow A by events
+    HIPC(hipStreamWaitEvent(qs.A, s->ev_in, 0));     // queues B and C follow A by events
   }
-  std::vector<Block> blks;
-  cut_blocks(s, s->lines_seen, n_lines, blks);
   bool notready = false;
   size_t i = 0;
   while (i < blks.size()) {
@@ -809,10 +828,12 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     if (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines < blks[i].lines) ++k;
     std::vector<Job> jobs(1);
     if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready)) != RX_OK) return r;
-    if ((r = launch_jobs(jobs, Queues{s->stA, s->stB, s->st}, s)) != RX_OK) return r;
+    if ((r = launch_jobs(jobs, qs, s)) != RX_OK) return r;
     i = k;
   }
   if (!is_device_ptr) HIPC(hipEventRecord(s->ev_stage, s->st));   // last reader of the staging buffer
+  HIPC(hipEventRecord(s->ev_last, s->st));
+  s->st_only_tail = one_queue;
   s->lines_seen += n_lines;
   s->cnt.lines_pushed += n_lines;
   if (notready) return fail(RX_E_NOTREADY, "a block was scored with N <= B and no ridge; its scores are NaN");

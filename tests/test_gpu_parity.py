@@ -325,3 +325,32 @@ def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt):
     sa, sb = a.scores_host(), b.scores_host()
     assert np.all(np.isfinite(sa))
     assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))
+
+
+def test_push_pattern_and_queue_mode_do_not_change_scores(rxm):
+    # A lone one-block push to an idle stream runs on one HIP queue, other
+    # pushes over three; switching between the two must not change a bit:
+    # every block's arithmetic is fixed by the block, not by how it arrived.
+    import torch
+    B, S, BL = 64, 256, 16
+    cube = synth.sensor_cube(41, lines=8 * BL, samples=S, bands=B).cube
+    x = dev(cube)
+    ref = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                                       block_lines=BL))
+    ref.rx_push_lines(x)
+    ref.rx_sync()
+    want = ref.scores_host()
+    ref.rx_destroy()
+    st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                                      block_lines=BL))
+    l0 = 0
+    for nb, sync in [(1, True), (1, False), (3, False), (1, True), (1, False), (1, False)]:
+        st.rx_push_lines(x[l0:l0 + nb * BL])
+        l0 += nb * BL
+        if sync:
+            st.rx_sync()
+    st.rx_sync()
+    got = st.scores_host()
+    st.rx_destroy()
+    assert l0 == cube.shape[0]
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
