@@ -70,7 +70,7 @@ def phase_cus(nblk, px, ncu):
     merge kernels fill the GPU)."""
     ks = -(-BLOCK * (-(-SAMPLES // 64)) // 91)
     tiles = px // 64
-    return {"covariance": min(ncu, nblk * ks), "whiten_score": min(ncu - 32, max(1, tiles // 16)),
+    return {"covariance": min(ncu, nblk * ks), "whiten_score": min(ncu - 32, max(1, tiles // 8)),
             "factor": min(ncu, nblk), "merge": ncu}
 
 

@@ -652,7 +652,7 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
       // its LDS; leaving W2_FREE_CUS CUs out lets the next batch's merge and
       // factorisation (queued on another HIP stream) run beside the whitening
       const int navail = ncu > 4 * W2_FREE_CUS ? ncu - W2_FREE_CUS : ncu;
-      const int g = (int)std::max<int64_t>(1, std::min<int64_t>(navail, ntile / (2 * W2W)));
+      const int g = (int)std::max<int64_t>(1, std::min<int64_t>(navail, ntile / W2W));   // a tile per wave at least
       switch ((wprec * 16 + ns) * 8 + G) {
 #define RXK_W2(PV, N, GG)                                                                              \
   case (PV * 16 + N) * 8 + GG:                                                                         \
