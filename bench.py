@@ -353,8 +353,8 @@ def main():
                          "scales hardware byte counters under rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build's path runs on a single MI355X "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the scoring path runs on a single MI355X; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

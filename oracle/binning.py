@@ -9,8 +9,8 @@ leaving 280, and every four consecutive bands of those are summed into one
 band of the 70-band cube.  On a BIL cube [lines][bands][samples]:
     out[l][j][s] = sum over t < k of in[l][b0 + j k + t][s],  j < nb / k.
 The paper does not say how many bands go at each end; b0 (the first kept
-band) is a parameter and the reading b0 = 10 (ten each side) is listed in
-the design doc.  Counts are integers, so the sums are exact (int64 here)."""
+band) is a parameter; the reading taken is b0 = 10 (ten each side).  Counts
+are integers, so the sums are exact (int64 here)."""
 from __future__ import annotations
 
 import numpy as np

@@ -13,7 +13,7 @@ the squared Mahalanobis distance.  A threshold marks pixels whose score is
 above a configurable value; the paper normalises scores so the set's maximum
 is 1 before thresholding (same section).
 
-Readings taken where the paper is silent (each is listed in the design doc):
+Readings taken where the paper is silent:
   * covariance normaliser 1/(N - ddof), ddof = 0 by default;
   * optional ridge lambda = rho * tr(Sigma) / B added to the diagonal;
   * strict ">" for the threshold; relative mode compares delta / max(delta);

@@ -17,7 +17,7 @@ an integer decided by floating point, so every step here is taken in FP32 as
 the paper states (numpy's float32 square root and division are correctly
 rounded; the cast to float16 rounds to nearest even).
 
-Readings (listed in DESIGN.md):
+Readings taken where the paper is silent:
   * the normalisation divides the square roots by their maximum, so the
     header value is m = max sqrt(delta) (= sqrt(max delta): the square root
     is monotone and correctly rounded);
