@@ -237,6 +237,30 @@ def paper_workload(rx, torch, reps=5):
                         "transmission codes", "paper_s_per_cube": PAPER_CUBE_S, **out}
 
 
+def host_input(rx, torch, cube, steps=3):
+    """The same mixed-path step with the cube pushed from host memory: the
+    library copies it into its pinned buffer and then to the device, so
+    this rate includes both copies (PCIe-inclusive; never the headline)."""
+    cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=RIDGE,
+                         block_lines=BLOCK, window_lines=LINES)
+    st = rx.RxStream(cfg)
+    sc = torch.empty(cube.shape[0] * SAMPLES, dtype=torch.float32, device="cuda")
+    st.rx_push_lines(cube)
+    st.rx_scores(sc)
+    torch.cuda.synchronize()
+    st.rx_sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.rx_push_lines(cube)
+        st.rx_scores(sc)
+    torch.cuda.synchronize()
+    st.rx_sync()
+    t1 = time.perf_counter()
+    st.rx_destroy()
+    return {"px_per_s": steps * cube.shape[0] * SAMPLES / (t1 - t0), "ms_per_step": (t1 - t0) / steps * 1e3,
+            "bytes_per_step": int(cube.nbytes)}
+
+
 def latency(rx, torch, x, prec, nblocks):
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
                          ridge_rel=RIDGE, block_lines=0, window_lines=LINES)
@@ -378,6 +402,8 @@ def main():
     p50, p99 = latency(rx, torch, x, "bf16", 40)
     log(f"block latency (100 lines): p50 {p50:.3f} ms, p99 {p99:.3f} ms")
     tx = transmit(rx, torch, npx)
+    hin = host_input(rx, torch, cube)
+    log(f"host input (copy to pinned + H2D included): {hin['px_per_s']:.3e} px/s, {hin['ms_per_step']:.1f} ms/step")
     pw = paper_workload(rx, torch)
     log(f"paper workload (per cube): mixed {pw['bf16']['s_per_cube'] * 1e3:.3f} ms, "
         f"fp32 {pw['fp32']['s_per_cube'] * 1e3:.3f} ms (paper: {PAPER_CUBE_S} s on one SBC core)")
@@ -445,6 +471,7 @@ def main():
                                   "pixels": int(nref)},
         "serving": served,
         "transmit": tx,
+        "host_input": hin,
         "paper_workload": pw,
         "roofline": roof,
         "phases": phases,
