@@ -354,3 +354,47 @@ def test_push_pattern_and_queue_mode_do_not_change_scores(rxm):
     st.rx_destroy()
     assert l0 == cube.shape[0]
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_relative_mask_maximum_over_pending_after_partial_pops(rxm):
+    # The relative mask's maximum is over exactly the pending scores: after a
+    # partial pop, after a push on top of a partly popped set, and after a
+    # drain.  Every mask must equal delta > tau * max(pending), computed from
+    # a twin stream's scores (bit-identical: same blocks, same arithmetic).
+    B, S, BL = 48, 256, 12
+    cube = synth.sensor_cube(43, lines=6 * BL, samples=S, bands=B).cube
+    x = dev(cube)
+    cfg = dict(in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6, block_lines=BL)
+    st = rxm.RxStream(rxm.make_config(B, S, **cfg))
+    tw = rxm.RxStream(rxm.make_config(B, S, **cfg))
+    tau = 0.3
+
+    def expect(sc):
+        d = sc.astype(np.float64)
+        return d > tau * np.nanmax(d)
+
+    st.rx_push_lines(x[:2 * BL])
+    tw.rx_push_lines(x[:2 * BL])
+    tw.rx_sync()
+    s_all = tw.scores_host()
+    assert np.array_equal(st.mask_host(tau, rxm.RX_THR_REL_MAX), expect(s_all))
+    cut = s_all.size // 3
+    part = np.empty(cut, dtype=np.float32)
+    assert st.rx_scores(part) == cut                      # partial pop
+    assert np.array_equal(part.view(np.uint32), s_all[:cut].view(np.uint32))
+    rest = s_all[cut:]
+    assert np.array_equal(st.mask_host(tau, rxm.RX_THR_REL_MAX), expect(rest))
+    st.rx_push_lines(x[2 * BL:3 * BL])                     # pushed on top of a partly popped set
+    tw.rx_push_lines(x[2 * BL:3 * BL])
+    tw.rx_sync()
+    more = tw.scores_host()
+    both = np.concatenate([rest, more])
+    assert np.array_equal(st.mask_host(tau, rxm.RX_THR_REL_MAX), expect(both))
+    assert np.array_equal(st.scores_host().view(np.uint32), both.view(np.uint32))   # drained
+    st.rx_push_lines(x[3 * BL:6 * BL])                     # a fresh set
+    tw.rx_push_lines(x[3 * BL:6 * BL])
+    tw.rx_sync()
+    last = tw.scores_host()
+    assert np.array_equal(st.mask_host(tau, rxm.RX_THR_REL_MAX), expect(last))
+    st.rx_destroy()
+    tw.rx_destroy()
