@@ -91,9 +91,13 @@ typedef struct rx_counters {
   int64_t lines_pushed;     /* lines accepted so far */
   int64_t blocks;           /* blocks processed */
   int64_t singular_blocks;  /* blocks whose factorisation hit a non-positive pivot */
-  int64_t notready_blocks;  /* blocks scored while N <= B without a ridge */
+  int64_t notready_blocks;  /* blocks scored while N <= B without a ridge (or N <= ddof) */
   int64_t pending_px;       /* scores produced and not yet consumed by rx_scores */
-  int64_t window_px;        /* N, pixels in the current statistics window */
+  int64_t window_px;        /* N, pixels in the statistics window (finite pixels only) */
+  int64_t nonfinite_px;     /* float input: pixels with a NaN or infinite band (left out of the
+                               statistics, scored NaN, never marked) */
+  int64_t fp8_saturated;    /* FP8 E4M3 whitening: centred, band-scaled input values beyond the
+                               format's range (|v| > 464), stored as +-448 */
 } rx_counters;
 
 /* Fill *cfg with defaults for B bands and S samples: u16 input, 12-bit,
@@ -117,7 +121,13 @@ rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
  * updates the statistics and is then scored.  Scores join the stream's
  * pending FIFO in pixel order (p = line * S + sample).  Asynchronous.
  * RX_E_NOTREADY when a block is scored with N <= B and no ridge (its scores
- * are NaN, the statistics are still updated). */
+ * are NaN, the statistics are still updated).
+ * Float input: a pixel with any NaN or infinite band is left out of the
+ * statistics (N counts finite pixels only), scores NaN and is counted in
+ * rx_counters.nonfinite_px; the paper is silent on such input (Section
+ * "System Implementation / Detection Algorithm" takes every pixel).  The
+ * NOTREADY return above counts pushed pixels; blocks that non-finite pixels
+ * leave not ready are found on the device (NaN scores, notready_blocks). */
 rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_lines, int32_t is_device_ptr,
                         void* hip_stream);
 

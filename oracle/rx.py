@@ -17,7 +17,10 @@ Readings taken where the paper is silent:
   * covariance normaliser 1/(N - ddof), ddof = 0 by default;
   * optional ridge lambda = rho * tr(Sigma) / B added to the diagonal;
   * strict ">" for the threshold; relative mode compares delta / max(delta);
-  * top-k ties go to the lower pixel index.
+  * top-k ties go to the lower pixel index;
+  * float input: a pixel with any NaN or infinite band is not part of the
+    set (left out of mu, Sigma and N) and scores NaN; integer input cannot
+    hold such values.
 
 Algorithm chosen to differ from the GPU path on purpose: integer input gets
 exact integer moments (Python ints, correctly rounded division); float input
@@ -116,12 +119,24 @@ def scores(px: np.ndarray, mu: np.ndarray, cov: np.ndarray, chunk: int = 1 << 16
     return out
 
 
+def finite_pixels(px: np.ndarray) -> np.ndarray:
+    """bool per pixel row: every band finite (always true for integers)."""
+    x = np.asarray(px)
+    if np.issubdtype(x.dtype, np.integer):
+        return np.ones(x.shape[0], dtype=bool)
+    return np.isfinite(x).all(axis=1)
+
+
 def rx_batch(cube: np.ndarray, ddof: int = 0, rho: float = 0.0) -> np.ndarray:
-    """Global RX over one set of lines: statistics of every pixel of the
-    cube, then Eq. 1 for every pixel.  Returns scores in pixel order."""
+    """Global RX over one set of lines: statistics of every finite pixel of
+    the cube, then Eq. 1 for every pixel (NaN for the others).  Returns
+    scores in pixel order."""
     px = pixels(cube)
-    mu, cov = stats(px, ddof)
-    return scores(px, mu, regularise(cov, rho))
+    ok = finite_pixels(px)
+    mu, cov = stats(px[ok], ddof)
+    out = np.full(px.shape[0], np.nan)
+    out[ok] = scores(px[ok], mu, regularise(cov, rho))
+    return out
 
 
 # ---------------------------------------------------------------- masks

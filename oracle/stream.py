@@ -13,6 +13,9 @@ paper's per-cube detector when one block is one cube).
 This is the plain definition, recomputed from scratch for every block:
 exact integer moments for integer input, a two-pass FP64 pass over every
 pixel kept in the window for float input, and an LU solve for the scores.
+Float pixels with a NaN or infinite band are not part of the window (N
+counts the others), score NaN and are counted in `nonfinite`; a block is
+"notready" when N <= B without a ridge, or N <= ddof.
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ class RxStreamOracle:
         self.window_lines = window_lines
         self.block_lines = block_lines
         self.lines_seen = 0
+        self.nonfinite = 0        # float pixels with a non-finite band, over every push
         self.status = []          # per processed block: "ok" | "notready" | "singular"
         self._reset()
 
@@ -85,14 +89,16 @@ class RxStreamOracle:
                 self.s1 += s1
                 self.s2 += s2
             else:
-                self.float_px.append(px.astype(np.float64))
-                self.n += px.shape[0]
+                ok = rx.finite_pixels(px)
+                self.float_px.append(px[ok].astype(np.float64))
+                self.n += int(ok.sum())
+                self.nonfinite += int((~ok).sum())
             self.lines_seen = pos + take
             out.append(self._score_block(px))
         return np.concatenate(out) if out else np.zeros(0)
 
     def _score_block(self, px):
-        if self.n <= self.B and self.rho == 0.0:
+        if (self.n <= self.B and self.rho == 0.0) or self.n <= self.ddof:
             self.status.append("notready")
             return np.full(px.shape[0], np.nan)
         n, mu, cov = self.stats()
@@ -103,7 +109,10 @@ class RxStreamOracle:
             self.status.append("singular")
             return np.full(px.shape[0], np.nan)
         self.status.append("ok")
-        return rx.scores(px, mu, cov_r)
+        ok = rx.finite_pixels(px)
+        out = np.full(px.shape[0], np.nan)
+        out[ok] = rx.scores(px[ok], mu, cov_r)
+        return out
 
 
 def float_stats_chunked(chunks, ddof: int = 0):

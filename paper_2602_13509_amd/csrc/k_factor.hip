@@ -55,8 +55,11 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const double N = d.n_snap[b];
 
-  if (d.rho == 0.0 && N <= (double)B) {       // window too small: Sigma is singular
-    if (tid == 0) d.status[b] = 2;
+  if (tid == 0) d.clipflag[b] = 0;             // set by the whitening of this batch
+  // window too small: Sigma is singular (no ridge), or its normaliser is not
+  // positive (float input whose non-finite pixels left too few)
+  if ((d.rho == 0.0 && N <= (double)B) || !(N - (double)d.ddof > 0.0)) {
+    if (tid == 0) { d.status[b] = 2; atomicAdd(d.nsing + 1, 1u); }
     return;
   }
   const double den = N - (double)d.ddof;

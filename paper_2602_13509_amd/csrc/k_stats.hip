@@ -3,6 +3,9 @@
 // Algorithm": mean per band, covariance over all pixels of the set).
 //
 // Per block of lines:
+//   k_valid  -- float input only: marks the pixels whose bands are all finite
+//               and counts the others per line; those pixels stay out of
+//               every sum below (and score NaN)
 //   k_shift  -- centring shift c = mean of the block's first line per band
 //               (rounded to FP32 on mixed paths, so it is exact in both the
 //               FP32 centring and the FP64 merge).
@@ -19,7 +22,40 @@
 
 namespace rxk {
 
+// ---------------------------------------------------------------------------- validity (float input)
+// One workgroup per line of the batch; a thread walks the band rows of its
+// samples (coalesced across the wave), so the line is read once.
+template <int IN>
+__global__ void __launch_bounds__(NT) k_valid(LaunchSet ls) {
+  int line;
+  const int bi = find_batch(ls, blockIdx.x, line);
+  const BatchDesc& d = ls.d[bi];
+  using T = typename InT<IN>::T;
+  const T* xl = static_cast<const T*>(d.x) + (int64_t)line * d.B * d.S;
+  __shared__ uint32_t red[NT / 64];
+  uint32_t bad = 0;
+  for (int s = threadIdx.x; s < d.S; s += NT) {
+    bool ok = true;
+#pragma unroll 8
+    for (int k = 0; k < d.B; ++k) ok &= finite_val(xl[(int64_t)k * d.S + s]);
+    d.valid[(int64_t)line * d.S + s] = ok ? 1 : 0;
+    bad += ok ? 0u : 1u;
+  }
+  bad = wave_sum(bad);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    d.nbadl[line] = (int)t;
+    if (t) atomicAdd(d.cnt64, (unsigned long long)t);
+  }
+}
+
 // ---------------------------------------------------------------------------- shift
+// The shift is the mean of the block's first line (of its finite pixels for
+// float input; 0 when there are none): any finite value is exact in the
+// merge's correction, a close one keeps the centred products small.
 template <int IN, int P>
 __global__ void __launch_bounds__(NT) k_shift(LaunchSet ls) {
   int local;
@@ -34,9 +70,22 @@ __global__ void __launch_bounds__(NT) k_shift(LaunchSet ls) {
   if (band < d.B) {
     const T* row = static_cast<const T*>(d.x) + ((int64_t)b * d.blk_lines * d.B + band) * d.S;
     double s = 0.0;
-    for (int i = lane; i < d.S; i += 64) s += to_d(row[i]);
-    s = wave_sum(s);
-    c = s / (double)d.S;
+    if constexpr (IN == IN_U16) {
+      for (int i = lane; i < d.S; i += 64) s += to_d(row[i]);
+      s = wave_sum(s);
+      c = s / (double)d.S;
+    } else {
+      const uint8_t* vl = d.valid + (int64_t)b * d.blk_lines * d.S;
+      double cnt = 0.0;
+      for (int i = lane; i < d.S; i += 64) {
+        const bool ok = vl[i] != 0;
+        s += ok ? to_d(row[i]) : 0.0;
+        cnt += ok ? 1.0 : 0.0;
+      }
+      s = wave_sum(s);
+      cnt = wave_sum(cnt);
+      c = cnt > 0.0 ? s / cnt : 0.0;
+    }
     if (P != P_F64) c = (double)(float)c;
   }
   if (lane == 0) d.shift[(int64_t)b * d.Bp + band] = c;
@@ -105,6 +154,7 @@ __global__ void __launch_bounds__(NT) k_syrk(LaunchSet ls) {
     // ---- stage the chunk
     if (r < nrows) {
       const T* row = xb + ((int64_t)line * d.B + band) * d.S + s0;
+      const uint8_t* vrow = (IN == IN_U16) ? nullptr : d.valid + ((int64_t)b * d.blk_lines + line) * d.S + s0;
       for (int sg = 0; sg < segs; ++sg) {
         const int k0 = 8 * (seg0 + sg);
         T v[8];
@@ -116,7 +166,7 @@ __global__ void __launch_bounds__(NT) k_syrk(LaunchSet ls) {
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const bool ok = bvalid && (k0 + j < nvalid);
+          const bool ok = bvalid && (k0 + j < nvalid) && (IN == IN_U16 || vrow[k0 + j] != 0);
           S o;
           if constexpr (P == P_F64) {
             o = ok ? (to_d(v[j]) - shd) : 0.0;
@@ -243,9 +293,19 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
         }
       }
     }
-    return nvalid;
+    if constexpr (IN == IN_U16) {
+      return nvalid;
+    } else {
+      // float input: bits 16.. carry which of this thread's 8 samples are valid
+      const uint8_t* vl = d.valid + ((int64_t)b * d.blk_lines + line) * d.S + s0;
+      int vm = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) vm |= (k0 + j < nvalid && vl[k0 + j] != 0) ? (1 << j) : 0;
+      return nvalid | (vm << 16);
+    }
   };
-  auto store = [&](int buf, int nvalid) {
+  auto store = [&](int buf, int packed) {
+    const int nvalid = (IN == IN_U16) ? packed : (packed & 0xffff);
 #pragma unroll
     for (int q = 0; q < S2IT; ++q) {
       const int r = row_of(q);
@@ -255,7 +315,7 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
       S o[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const bool ok = (r < d.B) && (k0 + j < nvalid);
+        const bool ok = (r < d.B) && (k0 + j < nvalid) && (IN == IN_U16 || ((packed >> (16 + j)) & 1));
         float dv;
         if constexpr (IN == IN_F64) dv = (float)(vv[j] - (double)d.shift[(int64_t)b * d.Bp + r]);
         else dv = (float)vv[j] - shf[q];
@@ -610,7 +670,9 @@ constexpr int MAXBLK = 64;  // blocks per batch (reset bits are a 64-bit mask)
 // block mean m_b, e = m_b - shift, d = m_b - window mean before the block,
 // window sums after it, and per block the pairwise-update weight
 // N n_b / (N + n_b) (0 when the window was empty: the block's scatter
-// replaces the window's).
+// replaces the window's; -1 when the block has no finite pixel: the window
+// is left as it was).  n_b counts the block's finite pixels; the window
+// count N travels with the window sums (entry Bp).
 __global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
   int local;
   const int bi = find_batch(ls, blockIdx.x, local);
@@ -630,29 +692,44 @@ __global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
   }
   __syncthreads();
   if (w != 0 || k >= d.Bp) return;
-  double N = (double)d.n_in;
+  double N = d.s1_in[d.Bp];
   double s1 = in ? d.s1_in[k] : 0.0;
   for (int b = 0; b < d.nblk; ++b) {
-    const double nb = (double)blk_lines_of(d, b) * d.S;
+    const int lb = blk_lines_of(d, b);
+    double nb = (double)lb * d.S;
+    if (d.nbadl) {
+      int bad = 0;
+      for (int l = 0; l < lb; ++l) bad += d.nbadl[b * d.blk_lines + l];
+      nb -= (double)bad;
+    }
     if ((d.reset_bits >> b) & 1ull) { N = 0.0; s1 = 0.0; }
-    const double mb = sb[b][lane] / nb;
     const int64_t o = (int64_t)b * d.Bp + k;
-    d.ev[o] = in ? mb - shb[b][lane] : 0.0;
-    d.dv[o] = (in && N > 0.0) ? mb - s1 / N : 0.0;
-    if (k == 0) d.coef[b] = N > 0.0 ? N * nb / (N + nb) : 0.0;
-    s1 += sb[b][lane];
-    N += nb;
-    d.mu_snap[o] = in ? s1 / N : 0.0;
+    if (k == 0) d.nbv[b] = nb;
+    if (nb > 0.0) {
+      const double mb = sb[b][lane] / nb;
+      d.ev[o] = in ? mb - shb[b][lane] : 0.0;
+      d.dv[o] = (in && N > 0.0) ? mb - s1 / N : 0.0;
+      if (k == 0) d.coef[b] = N > 0.0 ? N * nb / (N + nb) : 0.0;
+      s1 += sb[b][lane];
+      N += nb;
+    } else {
+      d.ev[o] = 0.0;
+      d.dv[o] = 0.0;
+      if (k == 0) d.coef[b] = -1.0;
+    }
+    d.mu_snap[o] = (in && N > 0.0) ? s1 / N : 0.0;
     if (k == 0) d.n_snap[b] = N;
   }
   d.s1_out[k] = in ? s1 : 0.0;
+  if (k == 0) d.s1_out[d.Bp] = N;
 }
 
 // Matrix part: one workgroup per quarter of a lower 16x16 tile (4 rows x 16
 // columns, one entry per lane).  The four waves share out the blocks:
 // C_b = fixed-order FP64 sum of the split partials, M2_b = C_b - n_b e e^T
 // (exact shift correction), into LDS; then one wave runs the pairwise
-// update M2 <- M2 + M2_b + w d d^T (or M2 <- M2_b for an empty window),
+// update M2 <- M2 + M2_b + w d d^T (or M2 <- M2_b for an empty window; M2
+// unchanged for a block with no finite pixel),
 // snapshotting the window's scatter matrix after every block.
 template <typename PT>
 __global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
@@ -670,7 +747,7 @@ __global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
   const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
   if (live) {
     for (int b = w; b < d.nblk; b += MW) {
-      const double nb = (double)blk_lines_of(d, b) * d.S;
+      const double nb = d.nbv[b];
       const int ksb = ks_of(d, b);
       const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
       double c = 0.0;
@@ -686,7 +763,7 @@ __global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
     if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
     const int64_t o = (int64_t)b * d.Bp;
     const double wgt = d.coef[b];
-    m2 = (wgt > 0.0) ? m2 + mbl[b][lane] + wgt * d.dv[o + gi] * d.dv[o + gj] : mbl[b][lane];
+    if (wgt >= 0.0) m2 = (wgt > 0.0) ? m2 + mbl[b][lane] + wgt * d.dv[o + gi] * d.dv[o + gj] : mbl[b][lane];
     d.m2_snap[b * bp2 + e] = m2;
   }
   d.m2_out[e] = m2;
@@ -694,12 +771,20 @@ __global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
 
 }  // namespace rxk
 
-// Host entry used by the runtime: phase 0 centring shift, 1 covariance
-// product, 2 merge (vector then matrix part).  wg: workgroups of the phase
+// Host entry used by the runtime: phase 3 validity (float input, before
+// the others), 0 centring shift, 1 covariance product, 2 merge (vector then
+// matrix part).  wg: workgroups of the phase
 // (for phase 2: wg = vector workgroups, wg2 = matrix workgroups).
 extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const rxk::LaunchSet* ls, int wg,
                                        const rxk::LaunchSet* ls2, int wg2, hipStream_t st) {
   using namespace rxk;
+  if (phase == 3) {
+    if (wg <= 0) return hipSuccess;
+    if (in_type == IN_F32) hipLaunchKernelGGL(k_valid<IN_F32>, dim3(wg), dim3(NT), 0, st, *ls);
+    else if (in_type == IN_F64) hipLaunchKernelGGL(k_valid<IN_F64>, dim3(wg), dim3(NT), 0, st, *ls);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   if (phase == 2) {
     if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(MB * MW), 0, st, *ls);
     if (wg2 > 0) {

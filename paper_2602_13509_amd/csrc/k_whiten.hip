@@ -58,6 +58,8 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
     constexpr int LDB = MAXBW + PAD;
     __shared__ S dt[KC * LDB];
     const float* isc = d.iscale + (int64_t)b * Bp;
+    const uint8_t* vl = (IN == IN_U16) ? nullptr : d.valid + (int64_t)lineb * d.S + s0;
+    uint32_t nclip = 0;                               // FP8: operand values clipped at 448
     for (int it = tid; it < Bw * 8; it += NT) {
       const int k = it >> 3, k0 = 8 * (it & 7);
       float dv[8];
@@ -79,6 +81,11 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
           else c = ((float)v[j] - mhi) - mlo;
           dv[j] = (k0 + j < nvalid) ? c * sc : 0.0f;
         }
+        if constexpr (P == P_FP8) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (k0 + j < nvalid && (IN == IN_U16 || vl[k0 + j] != 0)) nclip += e4m3_clips(dv[j]);
+        }
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) dv[j] = 0.0f;
@@ -87,6 +94,7 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
       for (int j = 0; j < 8; ++j) dt[(k0 + j) * LDB + k] = to_storage<P>(dv[j]);
     }
     __syncthreads();
+    if constexpr (P == P_FP8) wave_count(d.cnt64 + 1, nclip);
     if (16 * w >= nvalid) return;
     const S* wl = static_cast<const S*>(d.wlp) + (int64_t)b * Bp * Bw;
     const int nsteps = Bw / 32;
@@ -153,6 +161,9 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
   dl += __shfl_xor(dl, 16, 64);
   dl += __shfl_xor(dl, 32, 64);
   if (kg == 0 && 16 * w + n < nvalid) {
+    if constexpr (IN != IN_U16) {                      // a pixel with a non-finite band scores NaN
+      if (d.valid[(int64_t)lineb * d.S + s0 + 16 * w + n] == 0) dl = A(__builtin_nan(""));
+    }
     if constexpr (F64OUT) static_cast<double*>(d.scores)[out0 + 16 * w + n] = dl;
     else static_cast<float*>(d.scores)[out0 + 16 * w + n] = dl;
   }
@@ -246,10 +257,10 @@ template <> __device__ __forceinline__ void store_scores<4>(float* p, const floa
 }
 
 // Pixel groups per tile: four where the operand tile fits the register
-// budget without spilling (16-bit operands up to 288 bands, FP8 up to 192),
+// budget without spilling (16-bit operands up to 288 bands, FP8 up to 160),
 // two otherwise.
 __host__ __device__ constexpr int w2_groups(int p, int ns) {
-  return (p == P_FP8) ? (ns <= 6 ? 4 : 2) : (ns <= 9 ? 4 : 2);
+  return (p == P_FP8) ? (ns <= 5 ? 4 : 2) : (ns <= 9 ? 4 : 2);
 }
 
 // ls.wg0 holds the prefix of tiles per batch (not workgroups).  NS is the
@@ -387,11 +398,13 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
 
     int64_t t = tb0 + wv;
     const int64_t tend = tb0 + nseg;
+    bool clipped = false;                                       // FP8: a value beyond the format's range
     for (; t < tend; t += W2W) {
       load_raw(t);
       const int smp = TP * (int)(t % tpl) + G * n;
       const bool ok = smp < Sm;
       F xf[G][NS];
+      uint32_t top = 0;                                         // FP8: bit 8q+7 set if a byte coded +-448
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
         // re-read per tile: hoisting these tile-invariant values would hold
@@ -416,6 +429,13 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
 #pragma unroll
           for (int j = 0; j < 8; ++j) c[j] = __builtin_fmaf((float)raw[st][j].at(g), is[j], qh[j]) + ql[j];
           xf[g][st] = cvt_frag<P>(c);
+          if constexpr (P == P_FP8) {
+            // a byte coding +-448, the largest finite value, is where
+            // clipped values land (so do values in (432, 464], which round to it)
+            const uint2 w = __builtin_bit_cast(uint2, xf[g][st]);
+            const uint32_t x0 = (w.x & 0x7F7F7F7Fu) ^ 0x7E7E7E7Eu, x1 = (w.y & 0x7F7F7F7Fu) ^ 0x7E7E7E7Eu;
+            top |= ((x0 - 0x01010101u) & ~x0) | ((x1 - 0x01010101u) & ~x1);
+          }
         }
       }
 
@@ -458,8 +478,38 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
         dl[g] += __shfl_xor(dl[g], 32, 64);
       }
       if (kg == 0 && ok) store_scores<G>(&out[(t / tpl) * Sm + smp], dl);
+      if constexpr (P == P_FP8) clipped |= (ok && (top & 0x80808080u) != 0);
     }
+    // rare: a value of this segment was clipped; k_fp8_clips counts the
+    // block's clipped values exactly afterwards
+    if constexpr (P == P_FP8)
+      if (__ballot(clipped) != 0ull && lane == 0) d.clipflag[b] = 1;
   }
+}
+
+// Exact count of the FP8 operand values that k_whiten2 clipped, for the
+// blocks it flagged (none in the usual case: every workgroup then exits at
+// once).  One workgroup per line; the centred, band-scaled value is formed
+// exactly as k_whiten2 forms it.
+__global__ void __launch_bounds__(NT) k_fp8_clips(LaunchSet ls) {
+  int line;
+  const int bi = find_batch(ls, blockIdx.x, line);
+  const BatchDesc& d = ls.d[bi];
+  const int b = min(line / d.blk_lines, d.nblk - 1);
+  if (d.status[b] != 0 || d.clipflag[b] == 0) return;
+  const int B = d.B, Bp = d.Bp, Sm = d.S;
+  const uint16_t* xl = static_cast<const uint16_t*>(d.x) + (int64_t)line * B * Sm;
+  const double* mu = d.mu_snap + (int64_t)b * Bp;
+  const float* isc = d.iscale + (int64_t)b * Bp;
+  uint32_t nclip = 0;
+  for (int k = 0; k < B; ++k) {
+    const double m = mu[k];
+    const float mh = (float)m, ml = (float)(m - (double)mh), is = isc[k];
+    const float qh = -(mh * is), ql = -(ml * is);
+    for (int s = threadIdx.x; s < Sm; s += NT)
+      nclip += e4m3_clips(__builtin_fmaf((float)xl[(int64_t)k * Sm + s], is, qh) + ql);
+  }
+  wave_count(d.cnt64 + 1, nclip);
 }
 
 // ---------------------------------------------------------------------------- masks
@@ -662,10 +712,16 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
                         RXK_W2(PV, 6, GG) RXK_W2(PV, 7, GG) RXK_W2(PV, 8, GG) RXK_W2(PV, 9, GG)
         RXK_W2P(P_BF16, 4) RXK_W2P(P_F16, 4) RXK_W2(P_BF16, 10, 2) RXK_W2(P_F16, 10, 2)
         RXK_W2(P_FP8, 1, 4) RXK_W2(P_FP8, 2, 4) RXK_W2(P_FP8, 3, 4) RXK_W2(P_FP8, 4, 4) RXK_W2(P_FP8, 5, 4)
-        RXK_W2(P_FP8, 6, 4) RXK_W2(P_FP8, 7, 2) RXK_W2(P_FP8, 8, 2) RXK_W2(P_FP8, 9, 2) RXK_W2(P_FP8, 10, 2)
+        RXK_W2(P_FP8, 6, 2) RXK_W2(P_FP8, 7, 2) RXK_W2(P_FP8, 8, 2) RXK_W2(P_FP8, 9, 2) RXK_W2(P_FP8, 10, 2)
 #undef RXK_W2P
 #undef RXK_W2
         default: return hipErrorInvalidValue;
+      }
+      if (wprec == P_FP8) {
+        LaunchSet c = t;                                        // one workgroup per line
+        for (int i = 0; i < c.nb; ++i)
+          c.wg0[i + 1] = c.wg0[i] + (c.d[i].nblk - 1) * c.d[i].blk_lines + c.d[i].last_lines;
+        hipLaunchKernelGGL(k_fp8_clips, dim3(c.wg0[c.nb]), dim3(NT), 0, st, c);
       }
     }
     if (o.nb == 0) return hipGetLastError();

@@ -215,6 +215,25 @@ __device__ __forceinline__ float wave_sum(float v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Add a per-lane count to a stream counter: one atomic per wave, and none
+// when the whole wave counted nothing (the usual case).
+__device__ __forceinline__ void wave_count(unsigned long long* ctr, uint32_t v) {
+  if (__ballot(v != 0u) == 0ull) return;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) atomicAdd(ctr, (unsigned long long)v);
+}
+// A finite value whose E4M3 rounding is clipped: above 464, the midpoint
+// between 448 and the next step (480) that the format lacks.
+__device__ __forceinline__ uint32_t e4m3_clips(float c) {
+  const float a = __builtin_fabsf(c);
+  return (a > 464.0f && a < __builtin_huge_valf()) ? 1u : 0u;
+}
+template <typename T> __device__ __forceinline__ bool finite_val(T v) { return __builtin_isfinite(v); }
+template <> __device__ __forceinline__ bool finite_val<uint16_t>(uint16_t) { return true; }
 
 // ------------------------------------------------------------------ batch descriptors
 // One batch = a run of consecutive blocks of one stream pushed together
@@ -235,7 +254,10 @@ struct BatchDesc {
   int ddof;
   double rho;             // ridge: lambda = rho * tr(Sigma) / B
   uint64_t reset_bits;    // bit b: block b starts a new statistics window
-  int64_t n_in;           // window pixel count before the batch
+  // non-finite input (float input only; null for 16-bit input): a pixel with
+  // a NaN or infinite band is left out of the statistics and scores NaN
+  uint8_t* valid;         // [lines of the batch][S] 1 = every band finite
+  int* nbadl;             // [lines of the batch] pixels with a non-finite band
   // statistics scratch
   double* shift;          // [nblk][Bp] per-block centring shift (FP32-representable on mixed paths)
   void* part;             // [nblk][ks][Bp*Bp] centred scatter partials, lower part (float, or double on FP64)
@@ -245,9 +267,11 @@ struct BatchDesc {
   double* n_snap;         // [nblk] window pixel count after block b
   double* ev;             // [nblk][Bp] block mean minus shift
   double* dv;             // [nblk][Bp] block mean minus the window mean before the block
-  double* coef;           // [nblk] pairwise-update weight N n_b / (N + n_b), 0 for an empty window
+  double* coef;           // [nblk] pairwise-update weight N n_b / (N + n_b), 0 for an empty window,
+                          // -1 for a block with no finite pixel (the window is unchanged)
+  double* nbv;            // [nblk] pixels of block b that enter the statistics
   // resident window state (ping-pong between batches)
-  const double* s1_in; double* s1_out;   // [Bp] raw band sums of the window
+  const double* s1_in; double* s1_out;   // [Bp + 1] raw band sums of the window, then its pixel count N
   const double* m2_in; double* m2_out;   // [Bp*Bp] scatter matrix of the window (lower)
   // factorisation
   double* w64;            // [nblk][Bp*Bp] W = L^{-1} S (row-major lower, FP64)
@@ -255,7 +279,10 @@ struct BatchDesc {
   float* iscale;          // [nblk][Bp] input scale 2^-e_k applied to centred values
   float* oscale;          // [nblk][Bp] output row scale 2^f_i
   int* status;            // [nblk] 0 ok, 1 singular, 2 not ready
-  unsigned int* nsing;    // stream counter of singular blocks
+  int* clipflag;          // [nblk] FP8 whitening of 16-bit input: 1 if a value of block b was clipped
+  unsigned int* nsing;    // stream counters: [0] singular blocks, [1] blocks scored while not ready
+  unsigned long long* cnt64;   // stream counters: [0] pixels with a non-finite band,
+                               // [1] FP8 operand values that saturated
   void* scores;           // scores of the batch's pixels (float, or double on FP64 whitening)
 };
 

@@ -154,10 +154,10 @@ struct Block {
 };
 
 struct Sizes {
-  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status, ev, coef;
+  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status, ev, coef, valid, nbadl;
 };
 
-static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
+static Sizes scratch_sizes(int B, int S, int in_type, int sp, int nblk, int blk_lines) {
   const int Bp = pad16(B), Bw = pad32(Bp);
   const int nsr = ceil_div(Bp, SUP), nsup = nsr * (nsr + 1) / 2;
   const int ks = splits_for(blk_lines, ceil_div(S, KC), sp);
@@ -173,9 +173,14 @@ static Sizes scratch_sizes(int B, int S, int sp, int nblk, int blk_lines) {
   z.w64 = (size_t)nblk * Bp * Bp * 8;
   z.wlp = (size_t)nblk * Bp * Bw * 4;
   z.scl = (size_t)nblk * Bp * 4;
-  z.status = (size_t)nblk * 4;
+  z.status = (size_t)nblk * 8;             // status, then the FP8 clip flags
   z.ev = (size_t)nblk * Bp * 8;
   z.coef = (size_t)nblk * 8;
+  // float input: per-pixel validity (by parity, read by the whitening) and
+  // per-line counts of pixels with a non-finite band
+  const bool fl = in_type != RX_IN_U16;
+  z.valid = fl ? (size_t)nblk * blk_lines * S : 0;
+  z.nbadl = fl ? (size_t)nblk * blk_lines * 4 : 0;
   return z;
 }
 
@@ -201,17 +206,19 @@ struct rx_stream {
   int npar = 1, par = 0, last_par = 0;    // parity sets of the per-batch buffers (queued batches alternate)
   rx_server* srv = nullptr;
   size_t footprint = 0;
-  // resident window state (ping-pong)
+  // resident window state (ping-pong): raw band sums then the pixel count N
+  // (Bp + 1 values), scatter matrix
   DevBuf s1[2], m2[2];
   int cur = 0;
-  int64_t N = 0;
+  int64_t N = 0;                          // pixels pushed into the window (N on the device is lower
+                                          // when float input holds non-finite pixels)
   int64_t lines_seen = 0;
   // batch scratch
-  DevBuf nsing, evb, dvb, coefb, shift, part, psum;
+  DevBuf nsing, evb, dvb, coefb, nbvb, nbadl, shift, part, psum;
   // by parity: a batch's M2 and count snapshots are read by its factor, and
   // its mean snapshot, W, scales and status by its whitening, while the next
   // batch's product and merge run on queue A
-  DevBuf m2s[2], nsnap[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2];
+  DevBuf m2s[2], nsnap[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2], valid[2];
   unsigned last_nsing = 0;
   // pending scores
   DevBuf pend[2];
@@ -300,10 +307,10 @@ static rx_status validate(const rx_config* c) {
 
 static size_t stream_bytes(const rx_config* c, int max_block_lines) {
   const int Bp = pad16(c->bands);
-  const Sizes z = scratch_sizes(c->bands, c->samples, c->syrk_prec, 1, std::max(1, max_block_lines));
-  const size_t state = 2 * ((size_t)Bp * 8 + (size_t)Bp * Bp * 8);
+  const Sizes z = scratch_sizes(c->bands, c->samples, c->in_type, c->syrk_prec, 1, std::max(1, max_block_lines));
+  const size_t state = 2 * ((size_t)(Bp + 1) * 8 + (size_t)Bp * Bp * 8);
   const size_t scr = z.shift + z.part + z.psum + z.mu + z.m2 + z.nsnap + z.w64 + z.wlp + 2 * z.scl + z.status +
-                     2 * z.ev + z.coef;
+                     2 * z.ev + 2 * z.coef + 2 * z.valid + z.nbadl;
   const size_t esz = c->whiten_prec == RX_FP64 ? 8 : 4;
   const size_t pend = 2 * (size_t)std::max(1, max_block_lines) * c->samples * esz;
   return state + scr + pend;
@@ -332,7 +339,7 @@ static void free_stream(rx_stream* s) {
                     &s->nsnap[1], &s->mu[0],
                     &s->mu[1], &s->m2s[0], &s->nsnap[0], &s->w64[0], &s->w64[1], &s->wlp[0], &s->wlp[1], &s->isc[0],
                     &s->isc[1], &s->osc[0], &s->osc[1], &s->status[0], &s->status[1], &s->evb, &s->dvb, &s->coefb,
-                    &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
+                    &s->nbvb, &s->valid[0], &s->valid[1], &s->nbadl, &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
   for (DevBuf* b : bufs) dev_free(*b);
   if (s->host_pin) (void)hipHostFree(s->host_pin);
   s->host_pin = nullptr;
@@ -353,7 +360,7 @@ static void free_stream(rx_stream* s) {
 }
 
 static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
-  const Sizes z = scratch_sizes(s->B, s->S, s->sp, nblk, blk_lines);
+  const Sizes z = scratch_sizes(s->B, s->S, s->in_type, s->sp, nblk, blk_lines);
   rx_status r;
   if ((r = dev_ensure(s->shift, z.shift, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->part, z.part, s->st)) != RX_OK) return r;
@@ -374,6 +381,7 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
     if ((r = dev_ensure(s->isc[q], z.scl, s->st)) != RX_OK) return r;
     if ((r = dev_ensure(s->osc[q], z.scl, s->st)) != RX_OK) return r;
     if ((r = dev_ensure(s->status[q], z.status, s->st)) != RX_OK) return r;
+    if (z.valid && (r = dev_ensure(s->valid[q], z.valid, s->st)) != RX_OK) return r;
   }
   // buffers zeroed on queue C must be clear before queue B's factor writes
   // them (only after a growth: otherwise B must not wait behind C)
@@ -384,6 +392,8 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   if ((r = dev_ensure(s->evb, z.ev, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->dvb, z.ev, s->st)) != RX_OK) return r;
   if ((r = dev_ensure(s->coefb, z.coef, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->nbvb, z.coef, s->st)) != RX_OK) return r;
+  if (z.nbadl && (r = dev_ensure(s->nbadl, z.nbadl, s->st)) != RX_OK) return r;
   return RX_OK;
 }
 
@@ -447,7 +457,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
                        &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last};
   for (hipEvent_t* e : evs)
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
-  const size_t s1b = (size_t)s->Bp * 8, m2b = (size_t)s->Bp * s->Bp * 8;
+  const size_t s1b = (size_t)(s->Bp + 1) * 8, m2b = (size_t)s->Bp * s->Bp * 8;
   for (int i = 0; i < 2; ++i) {
     if ((r = dev_ensure(s->s1[i], s1b, s->st)) != RX_OK) return bail(r);
     if ((r = dev_ensure(s->m2[i], m2b, s->st)) != RX_OK) return bail(r);
@@ -512,7 +522,7 @@ struct Job {
   BatchDesc d;
   int in_type, sp, wp, Bw;
   int par;
-  int wg_shift, wg_syrk, wg_merge, wg_mmat, wg_factor, wg_whiten;
+  int wg_valid, wg_shift, wg_syrk, wg_merge, wg_mmat, wg_factor, wg_whiten;
 };
 
 // Cut n_lines starting at stream line `pos` into blocks.
@@ -563,7 +573,6 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.vec_ok = ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0) && (((size_t)s->S * s->esz) % 16 == 0);
   d.ddof = s->cfg.ddof;
   d.rho = s->cfg.ridge_rel;
-  d.n_in = s->N;
   uint64_t rb = 0;
   for (int b = 0; b < nblk; ++b) {
     const Block& bk = blks[i0 + b];
@@ -572,10 +581,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
       s->N = 0;
     }
     s->N += (int64_t)bk.lines * s->S;
-    if (s->cfg.ridge_rel == 0.0 && s->N <= s->B) {
-      notready = true;
-      s->cnt.notready_blocks += 1;
-    }
+    if (s->cfg.ridge_rel == 0.0 && s->N <= s->B) notready = true;
   }
   d.reset_bits = rb;
   const int q = s->par;                     // parity set of this batch's buffers
@@ -589,6 +595,11 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.ev = static_cast<double*>(s->evb.p);
   d.dv = static_cast<double*>(s->dvb.p);
   d.coef = static_cast<double*>(s->coefb.p);
+  d.nbv = static_cast<double*>(s->nbvb.p);
+  if (s->in_type != RX_IN_U16) {
+    d.valid = static_cast<uint8_t*>(s->valid[q].p);
+    d.nbadl = static_cast<int*>(s->nbadl.p);
+  }
   d.s1_in = static_cast<const double*>(s->s1[s->cur].p);
   d.s1_out = static_cast<double*>(s->s1[1 - s->cur].p);
   d.m2_in = static_cast<const double*>(s->m2[s->cur].p);
@@ -598,7 +609,9 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.iscale = static_cast<float*>(s->isc[q].p);
   d.oscale = static_cast<float*>(s->osc[q].p);
   d.status = static_cast<int*>(s->status[q].p);
+  d.clipflag = d.status + nblk;
   d.nsing = static_cast<unsigned int*>(s->nsing.p);
+  d.cnt64 = reinterpret_cast<unsigned long long*>(static_cast<char*>(s->nsing.p) + 8);
   d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
 
   j.s = s;
@@ -606,6 +619,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.sp = s->sp;
   j.wp = s->wp;
   j.Bw = s->Bw;
+  j.wg_valid = s->in_type != RX_IN_U16 ? (int)lines : 0;
   j.wg_shift = nblk * (s->Bp / 4);
   j.wg_syrk = (whole_triangle(s->sp) ? 1 : d.nsup) * ((nblk - 1) * d.ks + d.ks_last);
   j.wg_merge = ceil_div(s->Bp, 64);
@@ -703,13 +717,17 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
   rx_status r = run_groups([](const Job& j) { return j.in_type * 16 + j.sp; },
                            [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
                              LaunchSet a, b, c, e;
+                             const int it = jobs[grp[g0]].in_type, sp = jobs[grp[g0]].sp;
+                             rx_status q;
+                             if ((q = prof_mark(prof, 0, true, qs.A)) != RX_OK) return q;
+                             if (it != RX_IN_U16) {        // validity pass first (float input)
+                               const int n0 = fill(a, grp, g0, g1, &Job::wg_valid);
+                               HIPC(rxk_launch_stats(it, sp, 3, &a, n0, nullptr, 0, qs.A));
+                             }
                              const int n1 = fill(a, grp, g0, g1, &Job::wg_shift);
                              const int n2 = fill(b, grp, g0, g1, &Job::wg_syrk);
                              const int n3 = fill(c, grp, g0, g1, &Job::wg_merge);
                              const int n4 = fill(e, grp, g0, g1, &Job::wg_mmat);
-                             const int it = jobs[grp[g0]].in_type, sp = jobs[grp[g0]].sp;
-                             rx_status q;
-                             if ((q = prof_mark(prof, 0, true, qs.A)) != RX_OK) return q;
                              HIPC(rxk_launch_stats(it, sp, 0, &a, n1, nullptr, 0, qs.A));
                              if ((q = prof_mark(prof, 0, false, qs.A)) != RX_OK) return q;
                              if ((q = prof_mark(prof, 1, true, qs.A)) != RX_OK) return q;
@@ -995,13 +1013,19 @@ extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, 
 static rx_status refresh_counters(rx_stream* s) {
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
-  unsigned ns = 0;
-  HIPC(hipMemcpy(&ns, s->nsing.p, sizeof ns, hipMemcpyDeviceToHost));
+  struct { unsigned ns, nr; unsigned long long bad, clip; } c{};
+  HIPC(hipMemcpy(&c, s->nsing.p, sizeof c, hipMemcpyDeviceToHost));
+  double n = 0.0;
+  HIPC(hipMemcpy(&n, static_cast<double*>(s->s1[s->cur].p) + s->Bp, sizeof n, hipMemcpyDeviceToHost));
+  const unsigned ns = c.ns;
   if (ns > s->last_nsing && s->sticky == RX_OK) s->sticky = RX_E_SINGULAR;
   s->last_nsing = ns;
   s->cnt.singular_blocks = ns;
+  s->cnt.notready_blocks = c.nr;
+  s->cnt.nonfinite_px = (int64_t)c.bad;
+  s->cnt.fp8_saturated = (int64_t)c.clip;
   s->cnt.pending_px = s->tail - s->head;
-  s->cnt.window_px = s->N;
+  s->cnt.window_px = (int64_t)n;
   return RX_OK;
 }
 
@@ -1064,14 +1088,15 @@ extern "C" rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
   const int B = s->B, Bp = s->Bp;
-  std::vector<double> s1(Bp), m2((size_t)Bp * Bp);
-  HIPC(hipMemcpy(s1.data(), s->s1[s->cur].p, (size_t)Bp * 8, hipMemcpyDeviceToHost));
+  std::vector<double> s1(Bp + 1), m2((size_t)Bp * Bp);
+  HIPC(hipMemcpy(s1.data(), s->s1[s->cur].p, (size_t)(Bp + 1) * 8, hipMemcpyDeviceToHost));
   HIPC(hipMemcpy(m2.data(), s->m2[s->cur].p, (size_t)Bp * Bp * 8, hipMemcpyDeviceToHost));
-  *n = s->N;
+  const int64_t N = (int64_t)s1[Bp];            // finite pixels in the window
+  *n = N;
   if (mean)
-    for (int k = 0; k < B; ++k) mean[k] = s->N > 0 ? s1[k] / (double)s->N : NAN;
+    for (int k = 0; k < B; ++k) mean[k] = N > 0 ? s1[k] / (double)N : NAN;
   if (cov) {
-    const double den = (double)(s->N - s->cfg.ddof);
+    const double den = (double)(N - s->cfg.ddof);
     for (int i = 0; i < B; ++i)
       for (int j = 0; j <= i; ++j) cov[(size_t)i * B + j] = cov[(size_t)j * B + i] = m2[(size_t)i * Bp + j] / den;
   }
@@ -1086,14 +1111,15 @@ extern "C" rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, c
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
   const int B = s->B, Bp = s->Bp;
-  std::vector<double> s1(Bp, 0.0), m2((size_t)Bp * Bp, 0.0);
+  std::vector<double> s1(Bp + 1, 0.0), m2((size_t)Bp * Bp, 0.0);
   if (n > 0) {
     const double den = (double)(n - s->cfg.ddof);
     for (int k = 0; k < B; ++k) s1[k] = mean[k] * (double)n;
     for (int i = 0; i < B; ++i)
       for (int j = 0; j <= i; ++j) m2[(size_t)i * Bp + j] = cov[(size_t)i * B + j] * den;
   }
-  HIPC(hipMemcpy(s->s1[s->cur].p, s1.data(), (size_t)Bp * 8, hipMemcpyHostToDevice));
+  s1[Bp] = (double)n;
+  HIPC(hipMemcpy(s->s1[s->cur].p, s1.data(), (size_t)(Bp + 1) * 8, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(s->m2[s->cur].p, m2.data(), (size_t)Bp * Bp * 8, hipMemcpyHostToDevice));
   s->N = n;
   return RX_OK;

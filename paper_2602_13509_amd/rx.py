@@ -47,7 +47,8 @@ class rx_config(C.Structure):
 
 class rx_counters(C.Structure):
     _fields_ = [("lines_pushed", C.c_int64), ("blocks", C.c_int64), ("singular_blocks", C.c_int64),
-                ("notready_blocks", C.c_int64), ("pending_px", C.c_int64), ("window_px", C.c_int64)]
+                ("notready_blocks", C.c_int64), ("pending_px", C.c_int64), ("window_px", C.c_int64),
+                ("nonfinite_px", C.c_int64), ("fp8_saturated", C.c_int64)]
 
 
 class RxError(RuntimeError):

@@ -61,3 +61,16 @@ def emulate_scores(px, mean, cov_r, w, fmt, with_scale=False):
         return delta
     mag = (np.abs(dq) @ np.abs(wq).T) * np.ldexp(1.0, f)[None, :]
     return delta, (np.abs(y) * mag).sum(axis=1)
+
+
+def fp8_clip_count(px, mean, cov_r):
+    """Centred, band-scaled input values that E4M3 clips (|v| > 464), formed
+    as the whitening kernel forms them (FP32 centring with the split mean,
+    exact power-of-two band scale)."""
+    sc = 1.0 / np.sqrt(np.diag(cov_r))
+    e = np.frexp(1.0 / sc)[1] - 1                       # floor(log2 sigma_k), as in emulate_scores
+    mhi = mean.astype(np.float32)
+    mlo = (mean - mhi.astype(np.float64)).astype(np.float32)
+    d = (px.astype(np.float32) - mhi[None, :]) - mlo[None, :]
+    dq = (d * np.ldexp(np.float32(1.0), -e)[None, :].astype(np.float32)).astype(np.float32)
+    return int(np.count_nonzero(np.abs(dq) > np.float32(464.0)))

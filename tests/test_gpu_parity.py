@@ -290,6 +290,11 @@ def test_lowp_whitening_matches_host_emulation(rxm, fmt, kind):
     say(f"  {kind} {fmt}: kernel vs emulation max |diff|/bound {np.max(e / bound):.3e}, "
         f"max rel {np.max(e / np.maximum(emu, 1e-3 * B)):.3e}")
     assert np.all(e <= bound)
+    if fmt == "fp8":
+        from lowp_emu import fp8_clip_count
+        clipped = st.rx_get_counters().fp8_saturated
+        say(f"  {kind} fp8: {clipped} operand values saturated")
+        assert clipped == fp8_clip_count(orx.pixels(cube), mean, cov)
 
 
 def test_determinism_bitwise(rxm):
@@ -300,8 +305,8 @@ def test_determinism_bitwise(rxm):
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
-@pytest.mark.parametrize("fmt", ["bf16", "fp16", "fp8"])
-def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt):
+@pytest.mark.parametrize("fmt,B", [("bf16", 270), ("fp16", 270), ("fp8", 270), ("fp8", 180)])
+def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt, B):
     # 16-bit rows with 16-byte aligned starts take the 32-pixel tile kernel;
     # the same lines pushed from a buffer offset by one element take the
     # chunk kernel.  Both centre, scale and round identically and run the same
@@ -309,7 +314,7 @@ def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt):
     # both routes) the scores must match bit for bit.  S = 200 leaves a
     # ragged last tile; 3 blocks put block boundaries inside workgroup ranges.
     import torch
-    B, S = 270, 200
+    S = 200
     cube = synth.sensor_cube(26, lines=90, samples=S, bands=B).cube
     say(f"tile vs chunk whitening {fmt}: 90x{S}x{B} u16, blocks of 40")
     a = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten=fmt, block_lines=40))

@@ -350,3 +350,50 @@ def test_served_stream_specs():
         assert 100 <= s.rate_lines_per_s <= 400
         assert np.all(np.diff(s.arrivals) > 0) and s.arrivals[-1] <= 30.0
         assert s.block_lines.min() >= 16 and s.block_lines.max() <= 128
+
+
+# ---------------------------------------------------------------- non-finite float pixels
+@pytest.mark.parametrize("block_lines", [0, 2])
+def test_nonfinite_pixels_are_not_part_of_the_set(block_lines):
+    # Float input holding small integers, with NaN / +-inf planted in some
+    # pixels (one of them in the first line): every other pixel must score
+    # exactly what the exact-rational brute force gives over the finite
+    # pixels pushed so far, the planted ones NaN, and the count must match.
+    L, B, S = 6, 3, 8
+    rng = np.random.default_rng(5)
+    cube = rng.integers(0, 9, size=(L, B, S)).astype(np.float64)
+    bad = {(0, 0, 1): np.nan, (1, 2, 5): np.inf, (3, 1, 0): -np.inf, (4, 0, 7): np.nan, (4, 2, 7): np.nan}
+    for (l, b, s), v in bad.items():
+        cube[l, b, s] = v
+    o = RxStreamOracle(B, S, block_lines=block_lines)
+    got = o.push(cube)
+    px = rx.pixels(cube)
+    fin = np.isfinite(px).all(axis=1)
+    assert o.nonfinite == int((~fin).sum()) == 4            # (4, 0, 7) and (4, 2, 7) are one pixel
+    assert np.array_equal(np.isnan(got), ~fin)
+    step = (block_lines or L) * S
+    for p0 in range(0, L * S, step):
+        seen = px[:p0 + step][fin[:p0 + step]]
+        exact = [float(v) for v in brute.exact_scores(seen.astype(np.int64).tolist())]
+        want = np.full(step, np.nan)
+        want[fin[p0:p0 + step]] = exact[len(exact) - int(fin[p0:p0 + step].sum()):]
+        ok = fin[p0:p0 + step]
+        assert _rel(got[p0:p0 + step][ok], want[ok]) <= 1e-12
+    assert o.n == int(fin.sum())
+
+
+def test_nonfinite_batch_equals_set_without_them():
+    rng = np.random.default_rng(6)
+    cube = rng.normal(size=(5, 4, 9))
+    cube[2, 1, 3] = np.nan
+    cube[0, 3, 8] = -np.inf
+    px = rx.pixels(cube)
+    fin = np.isfinite(px).all(axis=1)
+    got = rx.rx_batch(cube)
+    kept = px[fin]
+    # the set without the non-finite pixels, scored by the closed form
+    # delta = N h_pp - 1 of the hat matrix of [1 X] (ddof 0, no ridge)
+    x1 = np.hstack([np.ones((kept.shape[0], 1)), kept])
+    h = np.diag(x1 @ np.linalg.pinv(x1))
+    assert np.array_equal(np.isnan(got), ~fin)
+    assert _rel(got[fin], kept.shape[0] * h - 1.0) <= 1e-9
