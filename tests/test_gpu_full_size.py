@@ -99,8 +99,11 @@ def test_stress_cube_full_size_sampled(rxm):
             bound = 2.0 * 1024 * 2.0 ** -24 * scale + 1e-6 * np.maximum(emu, 1e-3 * B)
             e = np.abs(out[w] - emu)
             mx, p99 = err_summary(out[w], ref, B)
+            c = st.rx_get_counters()
             say(f"stress full size {w}: vs oracle max rel {mx:.3e}, p99 rel {p99:.3e} (reported); "
-                f"vs emulation max |diff|/bound {np.max(e / bound):.3e}")
+                f"vs emulation max |diff|/bound {np.max(e / bound):.3e}; "
+                f"{c.fp8_saturated} FP8-saturated values of {L * S * B} (reported)")
+            assert c.nonfinite_px == 0
             assert np.all(np.isfinite(out[w]))
             assert np.all(e <= bound)
         st.rx_destroy()
