@@ -118,6 +118,26 @@ def measured_traffic(phase):
 PROFILED_PUSHES = 5
 
 
+def measured_hbm_gbs(torch, mib=1024, reps=10):
+    """Achievable HBM bandwidth on this GPU: a device-to-device copy of mib
+    MiB (read + write = 2 mib MiB of traffic), median of reps timed copies."""
+    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return 2.0 * (mib << 20) / float(np.median(times)) / 1e9
+
+
 def run_path(rx, torch, x, prec, steps, warmup, label):
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
                          ridge_rel=RIDGE if prec in ("bf16", "fp16", "fp8") else 0.0, block_lines=BLOCK,
@@ -429,6 +449,9 @@ def main():
         log(f"reference copy: {args.copy_mib} MiB device to device")
         del src, dst
 
+    hbm_meas = measured_hbm_gbs(torch)
+    log(f"measured HBM bandwidth (1 GiB device copy): {hbm_meas:.0f} GB/s")
+
     cpu, ref = cpu_baseline(cube, args.cpu_seconds)
     nref = ref.size
     err = np.abs(sc_mix[:nref] - ref) / np.maximum(ref, 1e-3 * BANDS)
@@ -445,6 +468,9 @@ def main():
     dom = max(work, key=lambda p: per[p] * cus[p])
     roof = roofline(dom, work[dom], per[dom])
     roof["traffic"] = measured_traffic(dom)
+    if roof["bound"] == "hbm":
+        roof["peak_measured"] = hbm_meas
+        roof["frac_measured"] = roof["achieved"] / hbm_meas
     phases = {}
     for i, p in enumerate(PHASES):
         phases[p] = {"mixed_ms": per[p], "fp64_ms": (ms_64[i] / n_64[i]) if n_64[i] else None}
@@ -453,6 +479,7 @@ def main():
             phases[p].update({"bound": r["bound"], "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]})
             if r["bound"] == "hbm":
                 phases[p]["mfma_frac"] = r["mfma_frac"]
+                phases[p]["frac_measured"] = r["achieved"] / hbm_meas
 
     value = npx / t_mix
     rec = {
@@ -474,6 +501,7 @@ def main():
         "host_input": hin,
         "paper_workload": pw,
         "roofline": roof,
+        "hbm_copy_gbs": hbm_meas,
         "phases": phases,
         "cpu_baseline": cpu,
     }

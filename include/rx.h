@@ -84,8 +84,19 @@ typedef struct rx_config {
                              (blocks never straddle a window edge; 1000 = the paper's cube) */
   double ridge_rel;       /* rho >= 0: lambda = rho * trace(Sigma) / B is added to the diagonal */
   int32_t device;         /* HIP device ordinal */
-  int32_t flags;          /* reserved, must be 0 */
+  int32_t flags;          /* RX_FLAG_CAUSAL or 0; other bits must be 0 */
 } rx_config;
+
+/* rx_config.flags: causal scoring.  Every block is scored with the window
+ * as it was before the block joined it (the paper scores a cube with
+ * statistics that include it, Section "System Implementation / Detection
+ * Algorithm"; the line-based detector it proposes, Section "Discussion /
+ * Performance", may instead score new lines against the lines already seen).
+ * A block that starts a window (the first block, or a reset) then has no
+ * statistics: its scores are NaN and it counts as not ready; so does a block
+ * whose earlier window holds N <= B pixels without a ridge.  Default off:
+ * update, then score. */
+#define RX_FLAG_CAUSAL 1
 
 typedef struct rx_counters {
   int64_t lines_pushed;     /* lines accepted so far */

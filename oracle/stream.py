@@ -16,6 +16,10 @@ pixel kept in the window for float input, and an LU solve for the scores.
 Float pixels with a NaN or infinite band are not part of the window (N
 counts the others), score NaN and are counted in `nonfinite`; a block is
 "notready" when N <= B without a ridge, or N <= ddof.
+
+causal=True takes the other reading of the line-based detector: every block
+is scored with the window as it was before the block joined it (a block that
+starts a window has no statistics and is "notready").
 """
 from __future__ import annotations
 
@@ -26,8 +30,9 @@ from . import rx
 
 class RxStreamOracle:
     def __init__(self, bands: int, samples: int, ddof: int = 0, rho: float = 0.0,
-                 window_lines: int = 0, block_lines: int = 0):
+                 window_lines: int = 0, block_lines: int = 0, causal: bool = False):
         self.B, self.S = bands, samples
+        self.causal = causal
         self.ddof, self.rho = ddof, rho
         self.window_lines = window_lines
         self.block_lines = block_lines
@@ -81,6 +86,8 @@ class RxStreamOracle:
             off += take
             px = rx.pixels(blk)
             is_int = np.issubdtype(px.dtype, np.integer)
+            if self.causal:
+                out.append(self._score_block(px))         # the window before the block
             if self.is_int is None:
                 self.is_int = is_int
             if is_int:
@@ -94,7 +101,8 @@ class RxStreamOracle:
                 self.n += int(ok.sum())
                 self.nonfinite += int((~ok).sum())
             self.lines_seen = pos + take
-            out.append(self._score_block(px))
+            if not self.causal:
+                out.append(self._score_block(px))         # update, then score
         return np.concatenate(out) if out else np.zeros(0)
 
     def _score_block(self, px):

@@ -3,7 +3,8 @@
 // Sigma^{-1}; it is applied as delta = |W (x - mu)|^2 with W lower
 // triangular and W^T W = (Sigma + lambda I)^{-1}.
 //
-// One 512-thread workgroup per block snapshot:
+// One 512-thread workgroup per block snapshot (causal mode adds one for the
+// window before the batch):
 //   Sigma = M2 / (N - ddof);  lambda = rho * tr(Sigma) / B;  Sigma_r = Sigma + lambda I
 //   equilibration R = S Sigma_r S with S = diag(Sigma_r,kk^{-1/2})  (unit diagonal)
 //   R = L L^T and W = L^{-1} S in one right-looking sweep over 16x16 tiles
@@ -56,10 +57,16 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
   const double N = d.n_snap[b];
 
   if (tid == 0) d.clipflag[b] = 0;             // set by the whitening of this batch
+  // the block this slot scores (causal mode: slot b scores block b + 1, the
+  // extra slot nblk block 0, the last slot none in this batch); the stream's
+  // singular / not-ready counters count scored blocks
+  const int sbk = !d.causal ? b : (b == d.nblk ? 0 : (b + 1 < d.nblk ? b + 1 : -1));
+  const bool counted = sbk >= 0 && !causal_empty(d, sbk);
+  if (tid == 0 && sbk >= 0 && causal_empty(d, sbk)) atomicAdd(d.nsing + 1, 1u);   // no window before it
   // window too small: Sigma is singular (no ridge), or its normaliser is not
   // positive (float input whose non-finite pixels left too few)
   if ((d.rho == 0.0 && N <= (double)B) || !(N - (double)d.ddof > 0.0)) {
-    if (tid == 0) { d.status[b] = 2; atomicAdd(d.nsing + 1, 1u); }
+    if (tid == 0) { d.status[b] = 2; if (counted) atomicAdd(d.nsing + 1, 1u); }
     return;
   }
   const double den = N - (double)d.ddof;
@@ -84,7 +91,7 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
   }
   __syncthreads();
   if (flag) {
-    if (tid == 0) { d.status[b] = 1; atomicAdd(d.nsing, 1u); }
+    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
     return;
   }
 
@@ -288,7 +295,7 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
     __syncthreads();
   }
   if (flag) {
-    if (tid == 0) { d.status[b] = 1; atomicAdd(d.nsing, 1u); }
+    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
     return;
   }
   // ---- W = L^{-1} S (FP64, row-major) and the whitening operand in the whitening

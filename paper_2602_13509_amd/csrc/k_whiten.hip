@@ -32,7 +32,8 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
   const BatchDesc& d = ls.d[bi];
   const int B = d.B, Bp = d.Bp, nT = Bp / 16;
   const int lineb = g / d.cpl;                        // line within the batch
-  const int b = min(lineb / d.blk_lines, d.nblk - 1);
+  const int bd = min(lineb / d.blk_lines, d.nblk - 1);  // block of the line
+  const int b = snap_slot(d, bd);                      // snapshot slot that scores it
   const int s0 = (g % d.cpl) * KC;
   const int nvalid = min(KC, d.S - s0);
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
@@ -42,7 +43,7 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
   constexpr bool F64OUT = (P == P_F64);
   const int64_t out0 = (int64_t)lineb * d.S + s0;
 
-  if (d.status[b] != 0) {                              // singular / not ready: NaN scores
+  if (d.status[b] != 0 || causal_empty(d, bd)) {      // singular / not ready: NaN scores
     if (tid < nvalid) {
       if (F64OUT) static_cast<double*>(d.scores)[out0 + tid] = __builtin_nan("");
       else static_cast<float*>(d.scores)[out0 + tid] = __builtin_nanf("");
@@ -295,13 +296,14 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
     const int64_t tpb = (int64_t)d.blk_lines * tpl;            // tiles per (full) block
     const int b = (int)min(tl / tpb, (int64_t)d.nblk - 1);
     const int64_t blk_end = ls.wg0[bi] + (int64_t)b * tpb + (int64_t)blk_lines_of(d, b) * tpl;
+    const int sb = snap_slot(d, b);                              // snapshot slot that scores block b
     const int64_t seg_end = min(T1, blk_end);
     const int64_t tb0 = cur - ls.wg0[bi];                      // segment, batch-relative tiles
     const int nseg = (int)(seg_end - cur);
     cur = seg_end;
     float* out = static_cast<float*>(d.scores);
 
-    if (d.status[b] != 0) {                                     // singular / not ready: NaN scores
+    if (d.status[sb] != 0 || causal_empty(d, b)) {              // singular / not ready: NaN scores
       for (int q = tid; q < nseg * TP; q += W2NT) {
         const int64_t t = tb0 + q / TP;
         const int smp = TP * (int)(t % tpl) + q % TP;
@@ -312,7 +314,7 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
 
     __syncthreads();                                            // previous segment's readers are done
     {
-      const S* wl = static_cast<const S*>(d.wlp) + (int64_t)b * Bp * Bw;
+      const S* wl = static_cast<const S*>(d.wlp) + (int64_t)sb * Bp * Bw;
       const int nfr = fr_off(nT);
       for (int it = tid; it < nfr * 64; it += W2NT) {
         const int f = it >> 6, l = it & 63;
@@ -324,7 +326,7 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
           // BF16 keeps FP32's exponent range, so the row's power-of-two output
           // scale folds into the staged operand exactly; the products then
           // come out already scaled (bit for bit what scaling them would give)
-          const float o = d.oscale[(int64_t)b * Bp + 16 * i + (l & 15)];
+          const float o = d.oscale[(int64_t)sb * Bp + 16 * i + (l & 15)];
           uint4 w = *reinterpret_cast<const uint4*>(src);
           uint32_t* q = reinterpret_cast<uint32_t*>(&w);
 #pragma unroll
@@ -340,9 +342,9 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
           *reinterpret_cast<uint2*>(wf + it * 8) = *reinterpret_cast<const uint2*>(src);
         }
       }
-      const double* mu = d.mu_snap + (int64_t)b * Bp;
-      const float* isc = d.iscale + (int64_t)b * Bp;
-      const float* osc = d.oscale + (int64_t)b * Bp;
+      const double* mu = d.mu_snap + (int64_t)sb * Bp;
+      const float* isc = d.iscale + (int64_t)sb * Bp;
+      const float* osc = d.oscale + (int64_t)sb * Bp;
       for (int k = tid; k < 16 * MAXT; k += W2NT) {
         float mh = 0.0f, ml = 0.0f, is = 0.0f;
         if (k < B) {
@@ -483,7 +485,7 @@ __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t 
     // rare: a value of this segment was clipped; k_fp8_clips counts the
     // block's clipped values exactly afterwards
     if constexpr (P == P_FP8)
-      if (__ballot(clipped) != 0ull && lane == 0) d.clipflag[b] = 1;
+      if (__ballot(clipped) != 0ull && lane == 0) d.clipflag[sb] = 1;
   }
 }
 
@@ -495,8 +497,9 @@ __global__ void __launch_bounds__(NT) k_fp8_clips(LaunchSet ls) {
   int line;
   const int bi = find_batch(ls, blockIdx.x, line);
   const BatchDesc& d = ls.d[bi];
-  const int b = min(line / d.blk_lines, d.nblk - 1);
-  if (d.status[b] != 0 || d.clipflag[b] == 0) return;
+  const int bd = min(line / d.blk_lines, d.nblk - 1);
+  const int b = snap_slot(d, bd);
+  if (d.status[b] != 0 || causal_empty(d, bd) || d.clipflag[b] == 0) return;
   const int B = d.B, Bp = d.Bp, Sm = d.S;
   const uint16_t* xl = static_cast<const uint16_t*>(d.x) + (int64_t)line * B * Sm;
   const double* mu = d.mu_snap + (int64_t)b * Bp;

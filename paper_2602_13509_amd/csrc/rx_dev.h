@@ -254,6 +254,8 @@ struct BatchDesc {
   int ddof;
   double rho;             // ridge: lambda = rho * tr(Sigma) / B
   uint64_t reset_bits;    // bit b: block b starts a new statistics window
+  int causal;             // 1: block b is scored with the window before it (snapshot slot b - 1;
+                          // slot nblk holds the window before the batch)
   // non-finite input (float input only; null for 16-bit input): a pixel with
   // a NaN or infinite band is left out of the statistics and scores NaN
   uint8_t* valid;         // [lines of the batch][S] 1 = every band finite
@@ -301,6 +303,15 @@ __device__ __forceinline__ int find_batch(const LaunchSet& ls, int wg, int& loca
 
 __device__ __forceinline__ int blk_lines_of(const BatchDesc& d, int b) {
   return b == d.nblk - 1 ? d.last_lines : d.blk_lines;
+}
+// Snapshot slot whose statistics score block b: the window after block b
+// (update, then score), or in causal mode the window before it.
+__device__ __forceinline__ int snap_slot(const BatchDesc& d, int b) {
+  return d.causal ? (b == 0 ? d.nblk : b - 1) : b;
+}
+// Causal mode: a block that starts a new window has no statistics before it.
+__device__ __forceinline__ bool causal_empty(const BatchDesc& d, int b) {
+  return d.causal && ((d.reset_bits >> b) & 1ull);
 }
 __device__ __forceinline__ int ks_of(const BatchDesc& d, int b) {
   return b == d.nblk - 1 ? d.ks_last : d.ks;

@@ -189,6 +189,7 @@ struct rx_stream {
   uint32_t magic = kMagic;
   rx_config cfg{};
   int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
+  int causal = 0;                         // blocks scored with the window before them
   size_t esz = 0;
   int dev = 0;
   // Three queues: A (centring shift, covariance product, merge), B (FP64
@@ -300,14 +301,15 @@ static rx_status validate(const rx_config* c) {
   if (c->ddof != 0 && c->ddof != 1) return fail(RX_E_ARG, "ddof must be 0 or 1");
   if (c->block_lines < 0 || c->window_lines < 0) return fail(RX_E_ARG, "block_lines and window_lines must be >= 0");
   if (!(c->ridge_rel >= 0.0) || !std::isfinite(c->ridge_rel)) return fail(RX_E_ARG, "ridge_rel must be finite and >= 0");
-  if (c->flags != 0) return fail(RX_E_ARG, "flags must be 0");
+  if ((c->flags & ~RX_FLAG_CAUSAL) != 0) return fail(RX_E_ARG, "unknown flags");
   if (c->in_type == RX_IN_U16 && (c->bit_depth < 0 || c->bit_depth > 16)) return fail(RX_E_ARG, "bit_depth must be in [0, 16]");
   return RX_OK;
 }
 
 static size_t stream_bytes(const rx_config* c, int max_block_lines) {
   const int Bp = pad16(c->bands);
-  const Sizes z = scratch_sizes(c->bands, c->samples, c->in_type, c->syrk_prec, 1, std::max(1, max_block_lines));
+  const int slots = 1 + ((c->flags & RX_FLAG_CAUSAL) ? 1 : 0);     // causal: the window before the block
+  const Sizes z = scratch_sizes(c->bands, c->samples, c->in_type, c->syrk_prec, slots, std::max(1, max_block_lines));
   const size_t state = 2 * ((size_t)(Bp + 1) * 8 + (size_t)Bp * Bp * 8);
   const size_t scr = z.shift + z.part + z.psum + z.mu + z.m2 + z.nsnap + z.w64 + z.wlp + 2 * z.scl + z.status +
                      2 * z.ev + 2 * z.coef + 2 * z.valid + z.nbadl;
@@ -415,6 +417,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
   s->Bw = pad32(s->Bp);
   s->S = cfg->samples;
   s->in_type = cfg->in_type;
+  s->causal = (cfg->flags & RX_FLAG_CAUSAL) ? 1 : 0;
   s->sp = cfg->syrk_prec;
   s->wp = cfg->whiten_prec;
   s->cpl = ceil_div(s->S, KC);
@@ -548,7 +551,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
                              Job& j, bool& notready) {
   const int nblk = (int)(i1 - i0);
   const int L = blks[i0].lines, last = blks[i1 - 1].lines;
-  rx_status r = alloc_scratch(s, nblk, L);
+  rx_status r = alloc_scratch(s, nblk + s->causal, L);
   if (r != RX_OK) return r;
   int64_t lines = 0;
   for (size_t i = i0; i < i1; ++i) lines += blks[i].lines;
@@ -580,8 +583,9 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
       rb |= 1ull << b;
       s->N = 0;
     }
+    if (s->causal && ((s->cfg.ridge_rel == 0.0 && s->N <= s->B) || s->N <= s->cfg.ddof)) notready = true;
     s->N += (int64_t)bk.lines * s->S;
-    if (s->cfg.ridge_rel == 0.0 && s->N <= s->B) notready = true;
+    if (!s->causal && s->cfg.ridge_rel == 0.0 && s->N <= s->B) notready = true;
   }
   d.reset_bits = rb;
   const int q = s->par;                     // parity set of this batch's buffers
@@ -609,7 +613,8 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.iscale = static_cast<float*>(s->isc[q].p);
   d.oscale = static_cast<float*>(s->osc[q].p);
   d.status = static_cast<int*>(s->status[q].p);
-  d.clipflag = d.status + nblk;
+  d.clipflag = d.status + nblk + s->causal;
+  d.causal = s->causal;
   d.nsing = static_cast<unsigned int*>(s->nsing.p);
   d.cnt64 = reinterpret_cast<unsigned long long*>(static_cast<char*>(s->nsing.p) + 8);
   d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
@@ -624,7 +629,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.wg_syrk = (whole_triangle(s->sp) ? 1 : d.nsup) * ((nblk - 1) * d.ks + d.ks_last);
   j.wg_merge = ceil_div(s->Bp, 64);
   j.wg_mmat = 4 * (s->Bp / 16) * (s->Bp / 16 + 1) / 2;
-  j.wg_factor = nblk;
+  j.wg_factor = nblk + s->causal;          // causal: also the window before the batch
   j.wg_whiten = (int)(lines * s->cpl);
 
   s->cur ^= 1;

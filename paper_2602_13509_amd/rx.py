@@ -20,6 +20,7 @@ RX_IN_U16, RX_IN_F32, RX_IN_F64 = 0, 1, 2
 RX_BIL = 0
 RX_FP64, RX_FP32, RX_BF16, RX_FP16, RX_FP8_E4M3 = 0, 1, 2, 3, 4
 RX_THR_ABS, RX_THR_REL_MAX, RX_THR_TOPK = 0, 1, 2
+RX_FLAG_CAUSAL = 1
 RX_MAX_BANDS = 320
 
 STATUS_NAMES = {0: "RX_OK", -1: "RX_E_ARG", -2: "RX_E_NOMEM", -3: "RX_E_NOTREADY", -4: "RX_E_SINGULAR",
@@ -131,7 +132,7 @@ def _stream_handle(stream) -> int:
 
 
 def make_config(bands: int, samples: int, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ddof=0,
-                ridge_rel=0.0, block_lines=0, window_lines=0, bit_depth=12, device=0) -> rx_config:
+                ridge_rel=0.0, block_lines=0, window_lines=0, bit_depth=12, device=0, causal=False) -> rx_config:
     cfg = rx_config()
     check(LIB.rx_config_init(C.byref(cfg), bands, samples))
     cfg.in_type = IN_TYPE[np.dtype(in_dtype)]
@@ -140,6 +141,7 @@ def make_config(bands: int, samples: int, in_dtype=np.uint16, syrk="bf16", white
     cfg.whiten_prec = PREC[whiten] if isinstance(whiten, str) else whiten
     cfg.ddof, cfg.ridge_rel = ddof, float(ridge_rel)
     cfg.block_lines, cfg.window_lines, cfg.device = block_lines, window_lines, device
+    cfg.flags = RX_FLAG_CAUSAL if causal else 0
     return cfg
 
 

@@ -50,8 +50,10 @@ def assert_mask(got_mask, ref_scores, tau_eff, tol, bands, label=""):
     assert bad.size == 0, f"{label}: mask differs at decided pixels {bad[:10]}"
 
 
-def oracle_stream_scores(cube, bands, samples, block_lines=0, window_lines=0, ddof=0, rho=0.0, pushes=None):
-    o = RxStreamOracle(bands, samples, ddof=ddof, rho=rho, window_lines=window_lines, block_lines=block_lines)
+def oracle_stream_scores(cube, bands, samples, block_lines=0, window_lines=0, ddof=0, rho=0.0, pushes=None,
+                         causal=False):
+    o = RxStreamOracle(bands, samples, ddof=ddof, rho=rho, window_lines=window_lines, block_lines=block_lines,
+                       causal=causal)
     if pushes is None:
         pushes = [cube.shape[0]]
     out, l0 = [], 0

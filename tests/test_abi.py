@@ -46,7 +46,7 @@ def test_config_defaults_and_host_validation():
     b = C.c_size_t()
     assert rx.LIB.rx_stream_footprint(C.byref(cfg), 100, C.byref(b)) == rx.RX_OK and b.value > 0
     for field, bad in (("bands", 0), ("bands", 321), ("samples", 0), ("syrk_prec", rx.RX_FP8_E4M3),
-                       ("whiten_prec", 9), ("ddof", 2), ("layout", 1), ("flags", 1), ("struct_size", 4)):
+                       ("whiten_prec", 9), ("ddof", 2), ("layout", 1), ("flags", 2), ("struct_size", 4)):
         c2 = rx.rx_config()
         C.memmove(C.byref(c2), C.byref(cfg), C.sizeof(cfg))
         setattr(c2, field, bad)

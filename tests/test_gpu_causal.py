@@ -1,0 +1,79 @@
+"""Causal scoring (RX_FLAG_CAUSAL) on the GPU through the C ABI, against the
+FP64 stream oracle in its causal mode: every block is scored with the window
+as it was before the block joined it.  Pushes of 10 and 14 lines in blocks of
+8 make the first block of each push take the window before the push (the
+extra snapshot slot); a 16-line reset window makes a block start a window in
+the middle of a push (no statistics: NaN, not ready)."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_scores, oracle_stream_scores, say
+from paper_2602_13509_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-9, 1e-11), "fp32": (1e-3, 1e-4), "bf16": (5e-2, 1e-2)}
+
+
+@pytest.fixture(scope="module")
+def rxm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_13509_amd import rx
+    return rx
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("window_lines", [0, 16])
+@pytest.mark.parametrize("S", [96, 128])
+def test_causal_matches_oracle(rxm, prec, window_lines, S):
+    L, B = 24, 40
+    cube = synth.sensor_cube(31, lines=L, samples=S, bands=B).cube
+    rho = 1e-6 if prec == "bf16" else 0.0
+    pushes = [10, 14]
+    say(f"causal {prec} window {window_lines} S {S}")
+    cfg = rxm.make_config(B, S, in_dtype=np.uint16, syrk=prec, whiten=prec, ridge_rel=rho, block_lines=8,
+                          window_lines=window_lines, causal=True)
+    st = rxm.RxStream(cfg)
+    codes = []
+    l0 = 0
+    for n in pushes:
+        codes.append(st.rx_push_lines(dev(cube[l0:l0 + n])))
+        l0 += n
+    st.rx_sync()
+    c = st.rx_get_counters()
+    got = st.scores_host(f64=(prec == "fp64"))
+    ref, o = oracle_stream_scores(cube, B, S, block_lines=8, window_lines=window_lines, rho=rho, pushes=pushes,
+                                  causal=True)
+    assert codes[0] == rxm.RX_E_NOTREADY                      # the first block has no window before it
+    assert c.notready_blocks == o.status.count("notready") >= 1
+    assert c.singular_blocks == 0
+    assert np.isnan(got[:8 * S]).all()
+    assert_scores(got, ref, B, *TOL[prec], label=f"causal {prec}")
+    st.rx_destroy()
+
+
+def test_causal_and_update_then_score_side_by_side(rxm):
+    # The same cube through both readings on two streams, each against the
+    # oracle in its own mode (one push, blocks of 4 lines).
+    L, B, S = 16, 24, 64
+    cube = synth.sensor_cube(32, lines=L, samples=S, bands=B).cube
+    a = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten="fp64", block_lines=4,
+                                     causal=True))
+    b = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten="fp64", block_lines=4))
+    a.rx_push_lines(dev(cube))
+    b.rx_push_lines(dev(cube))
+    a.rx_sync()
+    b.rx_sync()
+    ga, gb = a.scores_host(f64=True), b.scores_host(f64=True)
+    ra, _ = oracle_stream_scores(cube, B, S, block_lines=4, causal=True)
+    rb, _ = oracle_stream_scores(cube, B, S, block_lines=4)
+    assert_scores(ga, ra, B, *TOL["fp64"], label="causal fp64")
+    assert_scores(gb, rb, B, *TOL["fp64"], label="update-then-score fp64")
+    a.rx_destroy()
+    b.rx_destroy()

@@ -397,3 +397,34 @@ def test_nonfinite_batch_equals_set_without_them():
     h = np.diag(x1 @ np.linalg.pinv(x1))
     assert np.array_equal(np.isnan(got), ~fin)
     assert _rel(got[fin], kept.shape[0] * h - 1.0) <= 1e-9
+
+
+# ---------------------------------------------------------------- causal scoring
+@pytest.mark.parametrize("window_lines", [0, 4])
+def test_causal_blocks_scored_with_the_window_before_them(window_lines):
+    # Each block's scores equal exact-rational quadratic forms with the mean
+    # and covariance of the window's earlier lines only (Gauss-Jordan
+    # inverse); a block that starts a window has none and is not ready.
+    L, B, S, bl = 8, 3, 6, 2
+    cube = np.random.default_rng(8).integers(0, 9, size=(L, B, S)).astype(np.uint16)
+    o = RxStreamOracle(B, S, block_lines=bl, window_lines=window_lines, causal=True)
+    got = np.concatenate([o.push(cube[:4]), o.push(cube[4:])])
+    px = rx.pixels(cube)
+    want_status = []
+    for l0 in range(0, L, bl):
+        w0 = 0 if window_lines == 0 else (l0 // window_lines) * window_lines
+        prev = px[w0 * S:l0 * S]
+        blk = slice(l0 * S, (l0 + bl) * S)
+        if prev.shape[0] <= B:
+            want_status.append("notready")
+            assert np.isnan(got[blk]).all()
+            continue
+        want_status.append("ok")
+        mu, cov = brute.exact_stats(prev.tolist())
+        inv = brute.gauss_jordan_inverse(cov)
+        exact = []
+        for p in px[blk]:
+            d = [int(p[j]) - mu[j] for j in range(B)]
+            exact.append(float(sum(d[i] * inv[i][j] * d[j] for i in range(B) for j in range(B))))
+        assert _rel(got[blk], exact) <= 1e-12
+    assert o.status == want_status
