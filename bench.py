@@ -440,6 +440,10 @@ def main():
             f"{saturated['latency_ms']['p99']:.3f} ms")
         served = {"nominal": nominal, "saturated": saturated}
 
+    hbm_meas = measured_hbm_gbs(torch)
+    log(f"measured HBM bandwidth (1 GiB device copy): {hbm_meas:.0f} GB/s")
+
+    # the counter runs' reference: this copy must stay the program's last one
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -448,9 +452,6 @@ def main():
         torch.cuda.synchronize()
         log(f"reference copy: {args.copy_mib} MiB device to device")
         del src, dst
-
-    hbm_meas = measured_hbm_gbs(torch)
-    log(f"measured HBM bandwidth (1 GiB device copy): {hbm_meas:.0f} GB/s")
 
     cpu, ref = cpu_baseline(cube, args.cpu_seconds)
     nref = ref.size
