@@ -726,6 +726,9 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                              rx_status q;
                              if ((q = prof_mark(prof, 0, true, qs.A)) != RX_OK) return q;
                              if (it != RX_IN_U16) {        // validity pass first (float input)
+                               // valid[par] is read by the whitening of the batch
+                               // that last used this parity: wait for it first
+                               if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par], 0));
                                const int n0 = fill(a, grp, g0, g1, &Job::wg_valid);
                                HIPC(rxk_launch_stats(it, sp, 3, &a, n0, nullptr, 0, qs.A));
                              }

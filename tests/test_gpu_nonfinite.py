@@ -145,3 +145,24 @@ def test_fp8_saturation_count(rxm, dtype):
     st.rx_sync()
     assert st.rx_get_counters().fp8_saturated == len(far)
     st.rx_destroy()
+
+
+def test_many_pushes_in_flight_float_input(rxm):
+    # Twelve one-block pushes queued back to back (the caller's stream is not
+    # made to wait, the input stays resident): the validity buffers alternate
+    # by parity while earlier pushes' whitening may still read them.
+    import torch
+    cube = planted_cube(7, np.float32, L=48)
+    B, S = cube.shape[1], cube.shape[2]
+    x = dev(cube)
+    st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.float32, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                                      block_lines=4))
+    for l0 in range(0, 48, 4):
+        st.rx_push_lines(x[l0:l0 + 4], guard=False)
+    st.rx_sync()
+    torch.cuda.synchronize()
+    got = st.scores_host()
+    ref, o = oracle_stream_scores(cube, B, S, block_lines=4, rho=1e-6, pushes=[4] * 12)
+    assert st.rx_get_counters().nonfinite_px == o.nonfinite
+    assert_scores(got, ref, B, *TOL["bf16"], label="twelve pushes in flight")
+    st.rx_destroy()
