@@ -281,9 +281,12 @@ def host_input(rx, torch, cube, steps=3):
             "bytes_per_step": int(cube.nbytes)}
 
 
-def latency(rx, torch, x, prec, nblocks):
+def latency(rx, torch, x, prec, nblocks, causal=False):
+    """Push of one 100-line block (device input, GPU idle) to its scores in
+    the caller's device buffer: the time until the caller's stream has them
+    (statistics work the scores do not depend on may still be running)."""
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
-                         ridge_rel=RIDGE, block_lines=0, window_lines=LINES)
+                         ridge_rel=RIDGE, block_lines=0, window_lines=LINES, causal=causal)
     st = rx.RxStream(cfg)
     sc = torch.empty(BLOCK * SAMPLES, dtype=torch.float32, device="cuda")
     lat = []
@@ -293,7 +296,7 @@ def latency(rx, torch, x, prec, nblocks):
         t0 = time.perf_counter()
         st.rx_push_lines(blk)
         st.rx_scores(sc)
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()
         t1 = time.perf_counter()
         if k >= 3:
             lat.append(t1 - t0)
@@ -421,6 +424,8 @@ def main():
         t_32, _, _, _ = run_path(rx, torch, x, "fp32", k64, 1, "fp32")
     p50, p99 = latency(rx, torch, x, "bf16", 40)
     log(f"block latency (100 lines): p50 {p50:.3f} ms, p99 {p99:.3f} ms")
+    c50, c99 = latency(rx, torch, x, "bf16", 40, causal=True)
+    log(f"block latency, causal scoring (100 lines): p50 {c50:.3f} ms, p99 {c99:.3f} ms")
     tx = transmit(rx, torch, npx)
     hin = host_input(rx, torch, cube)
     log(f"host input (copy to pinned + H2D included): {hin['px_per_s']:.3e} px/s, {hin['ms_per_step']:.1f} ms/step")
@@ -495,6 +500,7 @@ def main():
         "mixed_over_fp64": None if args.skip_fp64 else t_64 / t_mix,
         "fp32_path": None if args.skip_fp64 else {"value": npx / t_32, "ms_per_step": t_32 * 1e3, "steps": k64},
         "latency_ms": {"block_lines": BLOCK, "p50": p50, "p99": p99},
+        "latency_ms_causal": {"block_lines": BLOCK, "p50": c50, "p99": c99},
         "score_error_vs_oracle": {"max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
                                   "pixels": int(nref)},
         "serving": served,

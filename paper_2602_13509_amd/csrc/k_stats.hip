@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
   if (w != 0 || k >= d.Bp) return;
   double N = d.s1_in[d.Bp];
   double s1 = in ? d.s1_in[k] : 0.0;
-  if (d.causal) {                        // slot nblk: the window before the batch
+  if (d.causal == 1) {                   // slot nblk: the window before the batch
     const bool r0 = d.reset_bits & 1ull;
     const int64_t o = (int64_t)d.nblk * d.Bp + k;
     d.mu_snap[o] = (in && !r0 && N > 0.0) ? s1 / N : 0.0;
@@ -765,7 +765,7 @@ __global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
   __syncthreads();
   if (w != 0 || !live) return;
   double m2 = d.m2_in[e];
-  if (d.causal) d.m2_snap[d.nblk * bp2 + e] = (d.reset_bits & 1ull) ? 0.0 : m2;   // window before the batch
+  if (d.causal == 1) d.m2_snap[d.nblk * bp2 + e] = (d.reset_bits & 1ull) ? 0.0 : m2;   // window before the batch
   for (int b = 0; b < d.nblk; ++b) {
     if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
     const int64_t o = (int64_t)b * d.Bp;

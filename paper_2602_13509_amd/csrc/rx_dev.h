@@ -254,8 +254,13 @@ struct BatchDesc {
   int ddof;
   double rho;             // ridge: lambda = rho * tr(Sigma) / B
   uint64_t reset_bits;    // bit b: block b starts a new statistics window
-  int causal;             // 1: block b is scored with the window before it (snapshot slot b - 1;
-                          // slot nblk holds the window before the batch)
+  int causal;             // block b is scored with the window before it (snapshot slot b - 1;
+                          // slot nblk holds the window before the batch): 1 = slot nblk is
+                          // formed by the merge and factored here, 2 = it is copied from the
+                          // previous batch's last slot (the src_* pointers) by k_copy_slot
+  const double* src_mu; const void* src_wlp; const double* src_w64;
+  const float* src_isc; const float* src_osc; const int* src_status;
+  int64_t wl_bytes;       // whitening operand bytes per slot (0 on the FP64 path)
   // non-finite input (float input only; null for 16-bit input): a pixel with
   // a NaN or infinite band is left out of the statistics and scores NaN
   uint8_t* valid;         // [lines of the batch][S] 1 = every band finite

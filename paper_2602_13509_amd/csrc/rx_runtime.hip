@@ -28,6 +28,7 @@ using namespace rxk;
 extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const LaunchSet* ls, int wg,
                                        const LaunchSet* ls2, int wg2, hipStream_t st);
 extern "C" hipError_t rxk_launch_factor(int wprec, const LaunchSet* ls, int wg, hipStream_t st);
+extern "C" hipError_t rxk_launch_copy_slot(const LaunchSet* ls, int nb, hipStream_t st);
 extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const LaunchSet* ls, int wg, int Bw,
                                         hipStream_t st);
 extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mode, double tau, int64_t k,
@@ -190,6 +191,11 @@ struct rx_stream {
   rx_config cfg{};
   int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
   int causal = 0;                         // blocks scored with the window before them
+  // causal: the previous batch's last snapshot slot (the window before the
+  // next batch, already factored), valid until the statistics are replaced
+  // or the snapshot buffers are reallocated
+  bool prev_valid = false;
+  int prev_par = 0, prev_slot = 0;
   size_t esz = 0;
   int dev = 0;
   // Three queues: A (centring shift, covariance product, merge), B (FP64
@@ -526,6 +532,8 @@ struct Job {
   int in_type, sp, wp, Bw;
   int par;
   int wg_valid, wg_shift, wg_syrk, wg_merge, wg_mmat, wg_factor, wg_whiten;
+  int copy = 0;           // causal: slot nblk is copied from the previous batch (k_copy_slot)
+  int fast = 0;           // ... and the whitening waits only for the input (one block, pipelined)
 };
 
 // Cut n_lines starting at stream line `pos` into blocks.
@@ -548,11 +556,17 @@ static void cut_blocks(const rx_stream* s, int64_t pos, int64_t n_lines, std::ve
 // Fill a job for blocks[i0, i1) of a push whose lines start at x.  Updates
 // the host copy of N and the pending tail; reserves scratch.
 static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Block>& blks, size_t i0, size_t i1,
-                             Job& j, bool& notready) {
+                             Job& j, bool& notready, bool allow_copy = false) {
   const int nblk = (int)(i1 - i0);
   const int L = blks[i0].lines, last = blks[i1 - 1].lines;
+  const int pp = s->prev_par;
+  const DevBuf* kept[6] = {&s->mu[pp], &s->wlp[pp], &s->w64[pp], &s->isc[pp], &s->osc[pp], &s->status[pp]};
+  size_t cap0[6];
+  for (int i = 0; i < 6; ++i) cap0[i] = kept[i]->cap;
   rx_status r = alloc_scratch(s, nblk + s->causal, L);
   if (r != RX_OK) return r;
+  for (int i = 0; i < 6; ++i)
+    if (kept[i]->cap != cap0[i]) s->prev_valid = false;   // reallocated: the previous slot is gone
   int64_t lines = 0;
   for (size_t i = i0; i < i1; ++i) lines += blks[i].lines;
   const int64_t npx = lines * s->S;
@@ -614,7 +628,22 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.oscale = static_cast<float*>(s->osc[q].p);
   d.status = static_cast<int*>(s->status[q].p);
   d.clipflag = d.status + nblk + s->causal;
-  d.causal = s->causal;
+  // causal: copy the previous batch's last slot (two parity sets, so this
+  // batch's merge and factor cannot overwrite it) or else form slot nblk here
+  const bool copy = s->causal && allow_copy && s->npar == 2 && s->prev_valid;
+  d.causal = s->causal ? (copy ? 2 : 1) : 0;
+  const int esz_w = s->wp == RX_FP64 ? 0 : s->wp == RX_FP32 ? 4 : s->wp == RX_FP8_E4M3 ? 1 : 2;
+  d.wl_bytes = (int64_t)s->Bp * s->Bw * esz_w;
+  if (copy) {
+    const int ps = s->prev_slot;
+    d.src_mu = static_cast<const double*>(s->mu[pp].p) + (int64_t)ps * s->Bp;
+    d.src_wlp = static_cast<const char*>(s->wlp[pp].p) + ps * d.wl_bytes;
+    d.src_w64 = static_cast<const double*>(s->w64[pp].p) + (int64_t)ps * s->Bp * s->Bp;
+    d.src_isc = static_cast<const float*>(s->isc[pp].p) + (int64_t)ps * s->Bp;
+    d.src_osc = static_cast<const float*>(s->osc[pp].p) + (int64_t)ps * s->Bp;
+    d.src_status = static_cast<const int*>(s->status[pp].p) + ps;
+  }
+  j.copy = copy ? 1 : 0;
   d.nsing = static_cast<unsigned int*>(s->nsing.p);
   d.cnt64 = reinterpret_cast<unsigned long long*>(static_cast<char*>(s->nsing.p) + 8);
   d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
@@ -629,7 +658,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.wg_syrk = (whole_triangle(s->sp) ? 1 : d.nsup) * ((nblk - 1) * d.ks + d.ks_last);
   j.wg_merge = ceil_div(s->Bp, 64);
   j.wg_mmat = 4 * (s->Bp / 16) * (s->Bp / 16 + 1) / 2;
-  j.wg_factor = nblk + s->causal;          // causal: also the window before the batch
+  j.wg_factor = nblk + (d.causal == 1 ? 1 : 0);   // causal, slot formed here: also the window before the batch
   j.wg_whiten = (int)(lines * s->cpl);
 
   s->cur ^= 1;
@@ -638,6 +667,11 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   s->last_par = q;
   s->par = (q + 1) % s->npar;
   s->cnt.blocks += nblk;
+  if (s->causal) {
+    s->prev_valid = true;
+    s->prev_par = q;
+    s->prev_slot = nblk - 1;
+  }
   return RX_OK;
 }
 
@@ -694,6 +728,25 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
   const bool piped = qs.A != qs.C;
   rx_stream* ps = piped ? jobs[0].s : nullptr;
   if (piped && jobs.size() != 1) return fail(RX_E_STATE, "pipelined launch of several jobs");
+  {
+    // causal batches whose window-before slot is the previous batch's last
+    // one: copy it on the whitening queue once the previous factorisation
+    // (the latest ev_fact) is done; this batch's merge and factor skip it
+    LaunchSet cs;
+    cs.nb = 0;
+    cs.wg0[0] = 0;
+    for (const Job& j : jobs)
+      if (j.copy) {
+        if (cs.nb == MAXB) return fail(RX_E_STATE, "too many batches in one launch");
+        cs.d[cs.nb] = j.d;
+        cs.wg0[cs.nb + 1] = cs.nb + 1;
+        ++cs.nb;
+      }
+    if (cs.nb > 0) {
+      if (piped) HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+      HIPC(rxk_launch_copy_slot(&cs, cs.nb, qs.C));
+    }
+  }
   auto run_groups = [&](auto key, auto launch) -> rx_status {
     std::vector<bool> done(jobs.size(), false);
     for (size_t a = 0; a < jobs.size(); ++a) {
@@ -742,6 +795,10 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                              HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, qs.A));
                              if ((q = prof_mark(prof, 1, false, qs.A)) != RX_OK) return q;
                              if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par], 0));
+                             // causal: the latest whitening (and the copy before it) read
+                             // the other parity's last slot, which this merge's successor
+                             // overwrites; waiting here keeps one batch between them
+                             if (piped && ps->causal) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par ^ 1], 0));
                              if ((q = prof_mark(prof, 2, true, qs.A)) != RX_OK) return q;
                              HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, qs.A));
                              if ((q = prof_mark(prof, 2, false, qs.A)) != RX_OK) return q;
@@ -766,7 +823,10 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
   if (r != RX_OK) return r;
   if (piped) {
     HIPC(hipEventRecord(ps->ev_fact, qs.B));
-    HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+    // a one-block causal batch whitens with the copied slot only: it needs
+    // the input, not this batch's statistics
+    if (jobs[0].fast) HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
+    else HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
   }
   r = run_groups([](const Job& j) { return (j.in_type * 16 + j.wp) * 1024 + j.Bw; },
                  [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
@@ -833,7 +893,7 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
   // first waits for it: its shift and covariance reuse the scratch that push
   // read on queue C.
   bool one_queue = false;
-  if (is_device_ptr && blks.size() == 1) {
+  if (is_device_ptr && blks.size() == 1 && !s->causal) {
     const hipError_t q = hipEventQuery(s->ev_last);
     if (q != hipSuccess && q != hipErrorNotReady) return fail(RX_E_DEVICE, "hipEventQuery failed: %s", hipGetErrorString(q));
     one_queue = q == hipSuccess;
@@ -853,7 +913,9 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     while (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines == blks[i].lines) ++k;
     if (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines < blks[i].lines) ++k;
     std::vector<Job> jobs(1);
-    if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready)) != RX_OK) return r;
+    if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready, true)) != RX_OK) return r;
+    // (float input: the whitening also reads the validity pass's output)
+    jobs[0].fast = jobs[0].copy && k - i == 1 && is_device_ptr && !one_queue && s->in_type == RX_IN_U16;
     if ((r = launch_jobs(jobs, qs, s)) != RX_OK) return r;
     i = k;
   }
@@ -1130,6 +1192,7 @@ extern "C" rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, c
   HIPC(hipMemcpy(s->s1[s->cur].p, s1.data(), (size_t)(Bp + 1) * 8, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(s->m2[s->cur].p, m2.data(), (size_t)Bp * Bp * 8, hipMemcpyHostToDevice));
   s->N = n;
+  s->prev_valid = false;          // causal: the next batch forms its window-before slot itself
   return RX_OK;
 }
 

@@ -77,3 +77,43 @@ def test_causal_and_update_then_score_side_by_side(rxm):
     assert_scores(gb, rb, B, *TOL["fp64"], label="update-then-score fp64")
     a.rx_destroy()
     b.rx_destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16", "fp8"])
+def test_causal_one_block_pushes(rxm, prec):
+    # One-block pushes queued back to back (input resident, the caller's
+    # stream not made to wait): from the second push on, the window-before
+    # slot is copied from the previous push and the whitening starts without
+    # waiting for the push's own statistics.  The scores must equal, bit for
+    # bit, those of one push of all the lines (same blocks, slots formed in
+    # the batch), and the FP64 / BF16 paths must match the oracle.
+    import torch
+    L, B, S, bl = 48, 64, 128, 4
+    cube = synth.sensor_cube(33, lines=L, samples=S, bands=B).cube
+    rho = 0.0 if prec == "fp64" else 1e-6
+    syrk = "fp64" if prec in ("fp64", "fp8") else prec
+    say(f"causal one-block pushes {prec}")
+    x = dev(cube)
+
+    def run(pushes):
+        st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk=syrk, whiten=prec, ridge_rel=rho,
+                                          block_lines=bl, window_lines=32, causal=True))
+        l0 = 0
+        for n in pushes:
+            st.rx_push_lines(x[l0:l0 + n], guard=False)
+            l0 += n
+        st.rx_sync()
+        torch.cuda.synchronize()
+        c = st.rx_get_counters()
+        out = st.scores_host(f64=(prec == "fp64"))
+        st.rx_destroy()
+        return out, c
+
+    a, ca = run([bl] * (L // bl))
+    b, cb = run([L])
+    assert np.array_equal(a.view(np.uint64 if prec == "fp64" else np.uint32),
+                          b.view(np.uint64 if prec == "fp64" else np.uint32))
+    ref, o = oracle_stream_scores(cube, B, S, block_lines=bl, window_lines=32, rho=rho, pushes=[L], causal=True)
+    assert ca.notready_blocks == cb.notready_blocks == o.status.count("notready") == 2
+    if prec != "fp8":
+        assert_scores(a, ref, B, *TOL[prec], label=f"causal one-block pushes {prec}")
