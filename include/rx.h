@@ -94,8 +94,10 @@ typedef struct rx_config {
  * Performance", may instead score new lines against the lines already seen).
  * A block that starts a window (the first block, or a reset) then has no
  * statistics: its scores are NaN and it counts as not ready; so does a block
- * whose earlier window holds N <= B pixels without a ridge.  Default off:
- * update, then score. */
+ * whose earlier window holds N <= B pixels without a ridge.  The scores of
+ * a one-block push of 16-bit device input then do not wait for that block's
+ * own statistics update (it runs alongside).  Default off: update, then
+ * score. */
 #define RX_FLAG_CAUSAL 1
 
 typedef struct rx_counters {
