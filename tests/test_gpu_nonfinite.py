@@ -147,22 +147,38 @@ def test_fp8_saturation_count(rxm, dtype):
     st.rx_destroy()
 
 
-def test_many_pushes_in_flight_float_input(rxm):
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_many_pushes_in_flight_float_input(rxm, prec):
     # Twelve one-block pushes queued back to back (the caller's stream is not
     # made to wait, the input stays resident): the validity buffers alternate
-    # by parity while earlier pushes' whitening may still read them.
+    # by parity while earlier pushes' whitening may still read them.  Scores
+    # do not depend on the push pattern, so they must equal those of one push
+    # of the same lines bit for bit; the FP64 path is also held to the oracle.
     import torch
     cube = planted_cube(7, np.float32, L=48)
     B, S = cube.shape[1], cube.shape[2]
     x = dev(cube)
-    st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.float32, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
-                                      block_lines=4))
-    for l0 in range(0, 48, 4):
-        st.rx_push_lines(x[l0:l0 + 4], guard=False)
-    st.rx_sync()
-    torch.cuda.synchronize()
-    got = st.scores_host()
-    ref, o = oracle_stream_scores(cube, B, S, block_lines=4, rho=1e-6, pushes=[4] * 12)
-    assert st.rx_get_counters().nonfinite_px == o.nonfinite
-    assert_scores(got, ref, B, *TOL["bf16"], label="twelve pushes in flight")
-    st.rx_destroy()
+    rho = 1e-6 if prec == "bf16" else 0.0
+
+    def run(pushes):
+        st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.float32, syrk=prec, whiten=prec, ridge_rel=rho,
+                                          block_lines=4))
+        l0 = 0
+        for n in pushes:
+            st.rx_push_lines(x[l0:l0 + n], guard=False)
+            l0 += n
+        st.rx_sync()
+        torch.cuda.synchronize()
+        c = st.rx_get_counters().nonfinite_px
+        out = st.scores_host(f64=(prec == "fp64"))
+        st.rx_destroy()
+        return out, c
+
+    a, ca = run([4] * 12)
+    b, cb = run([48])
+    assert np.array_equal(a.view(np.uint64 if prec == "fp64" else np.uint32),
+                          b.view(np.uint64 if prec == "fp64" else np.uint32))
+    ref, o = oracle_stream_scores(cube, B, S, block_lines=4, rho=rho, pushes=[4] * 12)
+    assert ca == cb == o.nonfinite
+    if prec == "fp64":
+        assert_scores(a, ref, B, *TOL["fp64"], label="twelve pushes in flight")
