@@ -159,3 +159,88 @@ def test_real_oracle_passes_every_check():
 def test_each_planted_mistake_is_caught(name):
     res = _run(Impl(**MUTANTS[name]))
     assert not all(res.values()), f"mutant '{name}' passed every pin: {res}"
+
+
+# ---------------------------------------------------------------- stream oracle: causal scoring, non-finite pixels
+from oracle.stream import RxStreamOracle  # noqa: E402
+
+
+def chk_causal_exact(cls):
+    """Causal block scores = exact-rational forms over the earlier lines."""
+    L, B, S, bl = 6, 3, 6, 2
+    cube = np.random.default_rng(8).integers(0, 9, size=(L, B, S)).astype(np.uint16)
+    o = cls(B, S, block_lines=bl, causal=True)
+    got = o.push(cube)
+    px = rx.pixels(cube)
+    for l0 in range(bl, L, bl):
+        prev = px[:l0 * S]
+        mu, cov = brute.exact_stats(prev.tolist())
+        inv = brute.gauss_jordan_inverse(cov)
+        for p in range(l0 * S, (l0 + bl) * S):
+            d = [int(px[p, j]) - mu[j] for j in range(B)]
+            want = float(sum(d[i] * inv[i][j] * d[j] for i in range(B) for j in range(B)))
+            if not abs(got[p] - want) <= 1e-12 * max(abs(want), 1e-300):
+                return False
+    return np.isnan(got[:bl * S]).all()
+
+
+def chk_nonfinite_exact(cls):
+    """Finite pixels score as the exact-rational set without the others."""
+    L, B, S = 4, 3, 8
+    cube = np.random.default_rng(5).integers(0, 9, size=(L, B, S)).astype(np.float64)
+    cube[1, 2, 5] = np.inf
+    cube[3, 0, 0] = np.nan
+    o = cls(B, S)
+    got = o.push(cube)
+    px = rx.pixels(cube)
+    fin = np.isfinite(px).all(axis=1)
+    exact = np.array([float(v) for v in brute.exact_scores(px[fin].astype(np.int64).tolist())])
+    return (np.array_equal(np.isnan(got), ~fin) and o.nonfinite == 2
+            and np.allclose(got[fin], exact, rtol=1e-12, atol=0))
+
+
+class CausalUsesUpdatedWindow(RxStreamOracle):
+    """Mistake: the causal flag ignored (the block joins the window first)."""
+    def __init__(self, *a, causal=False, **k):
+        super().__init__(*a, causal=False, **k)
+
+
+class NonfiniteStillCounted(RxStreamOracle):
+    """Mistake: non-finite pixels left out of the sums but still counted in N."""
+    def _score_block(self, px):
+        self.n += int((~rx.finite_pixels(px)).sum())
+        try:
+            return super()._score_block(px)
+        finally:
+            self.n -= int((~rx.finite_pixels(px)).sum())
+
+    def stats(self):
+        n, mu, cov = super().stats()
+        kept = np.concatenate(self.float_px)
+        d = kept - mu[None, :]
+        return n, mu, (d.T @ d) / self.n
+
+
+class NonfiniteScoredFinite(RxStreamOracle):
+    """Mistake: non-finite pixels excluded from the statistics but their
+    scores computed anyway (inf / nan arithmetic) instead of NaN."""
+    def _score_block(self, px):
+        out = super()._score_block(px)
+        bad = ~rx.finite_pixels(px)
+        out[bad] = 0.0
+        return out
+
+
+def test_stream_oracle_passes_its_new_pins():
+    assert chk_causal_exact(RxStreamOracle)
+    assert chk_nonfinite_exact(RxStreamOracle)
+
+
+@pytest.mark.parametrize("cls,chk", [(CausalUsesUpdatedWindow, chk_causal_exact),
+                                     (NonfiniteStillCounted, chk_nonfinite_exact),
+                                     (NonfiniteScoredFinite, chk_nonfinite_exact)])
+def test_stream_oracle_mutants_caught(cls, chk):
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        assert not chk(cls)
