@@ -305,7 +305,10 @@ def latency(rx, torch, x, prec, nblocks, causal=False):
     return float(np.median(lat)), float(np.quantile(lat, 0.99))
 
 
-def serving(rx, torch, seconds, replay_all_at_once):
+def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30):
+    """budget: the server's HBM budget in bytes, or a float in (0, 1): that
+    fraction of the streams' total footprint (rx_stream_footprint), so that
+    only some streams fit at once."""
     """Served form: 16 streams over every (S, B) in {320, 640, 1024} x {120,
     200, 270, 300} plus seeded repeats, Poisson block arrivals of 16-128 lines
     at 100-400 lines/s per stream, cumulative windows, BF16 path.  Each stream
@@ -313,17 +316,40 @@ def serving(rx, torch, seconds, replay_all_at_once):
     not change the work).  Blocks are submitted at their arrival times (or all
     at once) and the server is stepped continuously: whatever is queued joins
     the next batched launch while earlier launches are still running.
-    Latency = arrival -> completion seen by a non-blocking poll."""
+    Latency = arrival -> completion seen by a non-blocking poll.
+    With a budget too small for every stream, a stream that does not fit is
+    admitted (rx_init against the server) once finished streams have been
+    destroyed and their HBM released; its blocks wait meanwhile, and that
+    wait counts in their latency."""
     from paper_2602_13509_amd import synth
     specs = synth.served_streams(0, n_streams=16, duration_s=seconds)
-    srv = rx.RxServer(64 << 30, 16)
-    streams, cubes = [], []
+    streams, cubes, cfgs = [None] * len(specs), [], []
     for sp in specs:
         c = synth.sensor_cube(sp.seed, lines=128, samples=sp.samples, bands=sp.bands, chunk_lines=64).cube
         cubes.append(torch.from_numpy(c).cuda())
-        cfg = rx.make_config(sp.bands, sp.samples, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=RIDGE,
-                             block_lines=128)
-        streams.append(rx.RxStream(cfg, server=srv))
+        cfgs.append(rx.make_config(sp.bands, sp.samples, in_dtype=np.uint16, syrk="bf16", whiten="bf16",
+                                   ridge_rel=RIDGE, block_lines=128))
+    if isinstance(budget, float):
+        budget = int(budget * sum(rx.stream_footprint(c, 128) for c in cfgs))
+    srv = rx.RxServer(budget, 16)
+    held = [[] for _ in specs]            # blocks of a stream not admitted yet: (tag, lines)
+    left = [len(sp.block_lines) for sp in specs]
+    admitted_late = 0
+
+    def admit(late):
+        nonlocal admitted_late
+        for i in range(len(specs)):
+            if streams[i] is None and left[i] > 0:
+                try:
+                    streams[i] = rx.RxStream(cfgs[i], server=srv)
+                except rx.RxError as e:
+                    if e.status != rx.RX_E_BUDGET:
+                        raise
+                    continue
+                admitted_late += 1 if late else 0
+                for tg, n in held[i]:
+                    srv.rx_server_submit(streams[i], cubes[i][:n], tg)
+                held[i].clear()
     ev = sorted((0.0 if replay_all_at_once else float(t), i, int(n))
                 for i, sp in enumerate(specs) for t, n in zip(sp.arrivals, sp.block_lines))
     arrive, px_of, owner = {}, {}, {}
@@ -331,33 +357,49 @@ def serving(rx, torch, seconds, replay_all_at_once):
     lat, total_px = [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    admit(False)
     k, tag, launched = 0, 0, 0
     while len(lat) < len(ev):
         now = time.perf_counter() - t0
         while k < len(ev) and ev[k][0] <= now:
             t_arr, i, n = ev[k]
-            srv.rx_server_submit(streams[i], cubes[i][:n], tag)
+            if streams[i] is not None:
+                srv.rx_server_submit(streams[i], cubes[i][:n], tag)
+            else:
+                held[i].append((tag, n))
             arrive[tag] = t_arr
             px_of[tag] = n * specs[i].samples
             owner[tag] = i
             tag += 1
             k += 1
         launched += srv.rx_server_step()
+        freed = False
         for d in srv.rx_server_poll(block=False):
             lat.append(time.perf_counter() - t0 - arrive[d])
             total_px += px_of[d]
-            streams[owner[d]].rx_scores(outs[owner[d]])    # pop the block's scores (device to device)
+            i = owner[d]
+            streams[i].rx_scores(outs[i])    # pop the block's scores (device to device)
+            left[i] -= 1
+            if left[i] == 0 and budget < (64 << 30):
+                streams[i].scores_host()     # a finished stream leaves: its HBM goes back to the server
+                streams[i].rx_destroy()
+                streams[i] = False
+                freed = True
+        if freed:
+            admit(True)
         if now > seconds + 120.0:
             raise RuntimeError(f"served run did not drain: {len(lat)} of {len(ev)} blocks done")
     t_end = time.perf_counter() - t0
     for st in streams:
-        st.scores_host()                      # drain the FIFOs (not timed)
-        st.rx_destroy()
+        if st:
+            st.scores_host()                      # drain the FIFOs (not timed)
+            st.rx_destroy()
     srv.rx_server_destroy()
     lat = np.array(lat) * 1e3
     offered = sum(int(np.sum(sp.block_lines)) * sp.samples for sp in specs) / seconds
     return {"streams": len(specs), "blocks": len(ev), "arrival_window_s": seconds,
-            "all_at_once": replay_all_at_once, "px": int(total_px), "wall_s": t_end,
+            "all_at_once": replay_all_at_once, "hbm_budget_bytes": int(budget),
+            "streams_admitted_late": admitted_late, "px": int(total_px), "wall_s": t_end,
             "px_per_s": total_px / t_end, "offered_px_per_s": offered,
             "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99)),
                            "max": float(lat.max())}}
@@ -378,10 +420,13 @@ def cpu_baseline(cube, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    info = threadpool_info()
+    threads = max([p.get("num_threads", 1) for p in info] or [1])
+    blas = ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in info if p.get("user_api") == "blas"}))
     cores = len(os.sched_getaffinity(0))
     px = nb * BLOCK * SAMPLES
     return {"value": px / dt, "unit": "pixel-spectra/s", "cores": int(min(threads, cores)), "kind": "oracle",
+            "affinity_cores": cores, "blas": blas or None,
             "sample": f"first {nb} of 20 blocks ({nb * BLOCK} lines x {SAMPLES} x {BANDS}, exact integer "
                       f"statistics + LU solves, ridge {RIDGE}), {dt:.1f} s"}, np.concatenate(outs)
 
@@ -443,7 +488,11 @@ def main():
         saturated = serving(rx, torch, args.serve_seconds, True)
         log(f"served (16 streams, all blocks at once): {saturated['px_per_s']:.3e} px/s, p99 "
             f"{saturated['latency_ms']['p99']:.3f} ms")
-        served = {"nominal": nominal, "saturated": saturated}
+        tight = serving(rx, torch, args.serve_seconds, False, budget=0.5)
+        log(f"served (16 streams, nominal arrivals, HBM budget {tight['hbm_budget_bytes'] / 2**20:.0f} MiB = half "
+            f"their footprint; {tight['streams_admitted_late']} admitted late): {tight['px_per_s']:.3e} px/s, "
+            f"block latency p50 {tight['latency_ms']['p50']:.3f} ms, p99 {tight['latency_ms']['p99']:.3f} ms")
+        served = {"nominal": nominal, "saturated": saturated, "nominal_half_budget": tight}
 
     hbm_meas = measured_hbm_gbs(torch)
     log(f"measured HBM bandwidth (1 GiB device copy): {hbm_meas:.0f} GB/s")
