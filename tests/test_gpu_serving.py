@@ -150,3 +150,66 @@ def test_server_tags_in_launch_order_and_block_limit(rxm):
     assert_scores(got, ref, B, *TOL_BF16, label="served single stream")
     st.rx_destroy()
     srv.rx_server_destroy()
+
+
+def test_served_mix_with_causal_and_float_streams(rxm):
+    # Served streams batched into shared launches with the other readings:
+    # causal scoring (its window-before slot formed in the batch on the
+    # server, copied from the previous push when alone) and float input with
+    # non-finite pixels (the validity pass joins the shared launches).  Every
+    # stream must score bit for bit as alone; the FP64 ones match the oracle.
+    import torch
+    rng = np.random.default_rng(11)
+    specs = []   # (B, S, dtype, prec, causal, blocks)
+    for B, S, dt, prec, causal in [(200, 640, np.uint16, "bf16", True), (120, 320, np.float32, "fp64", False),
+                                   (270, 640, np.uint16, "bf16", False), (64, 256, np.float32, "fp64", True),
+                                   (96, 200, np.float64, "fp64", True)]:
+        blocks = [int(v) for v in rng.integers(8, 25, size=4)]
+        cube = synth.sensor_cube(200 + B, lines=sum(blocks), samples=S, bands=B).cube.astype(dt)
+        if dt != np.uint16:
+            n = cube.shape[0] * S
+            for p in rng.choice(n, size=n // 50, replace=False):
+                cube[p // S, rng.integers(B), p % S] = np.nan if p % 3 else np.inf
+        specs.append((B, S, dt, prec, causal, blocks, cube))
+
+    def cfg(B, S, dt, prec, causal, bl):
+        return rxm.make_config(B, S, in_dtype=dt, syrk=prec, whiten=prec, ridge_rel=1e-6 if prec == "bf16" else 0.0,
+                               block_lines=bl, causal=causal)
+
+    dcubes = [dev(s[6]) for s in specs]
+    alone = []
+    for (B, S, dt, prec, causal, blocks, cube), dc in zip(specs, dcubes):
+        st = rxm.RxStream(cfg(B, S, dt, prec, causal, 0))
+        l0 = 0
+        for n in blocks:
+            st.rx_push_lines(dc[l0:l0 + n])
+            l0 += n
+        st.rx_sync()
+        alone.append(st.scores_host(f64=(prec == "fp64")))
+        st.rx_destroy()
+
+    srv = rxm.RxServer(8 << 30, 16)
+    served = [rxm.RxStream(cfg(B, S, dt, prec, causal, 64), server=srv) for (B, S, dt, prec, causal, _, _) in specs]
+    order = [(i, j) for i, s in enumerate(specs) for j in range(len(s[5]))]
+    rng.shuffle(order)
+    nxt = [0] * len(specs)
+    starts = [np.concatenate([[0], np.cumsum(s[5])]) for s in specs]
+    tag = 0
+    for i, _ in order:
+        j = nxt[i]
+        nxt[i] += 1
+        srv.rx_server_submit(served[i], dcubes[i][int(starts[i][j]):int(starts[i][j + 1])], tag)
+        tag += 1
+    while srv.rx_server_queued()[0] > 0:
+        srv.rx_server_step()
+    assert sorted(srv.rx_server_poll(block=True)) == list(range(tag))
+    torch.cuda.synchronize()
+    for k, ((B, S, dt, prec, causal, blocks, cube), st) in enumerate(zip(specs, served)):
+        got = st.scores_host(f64=(prec == "fp64"))
+        w = np.uint64 if prec == "fp64" else np.uint32
+        assert np.array_equal(got.view(w), alone[k].view(w)), f"stream {k} (B={B}, S={S}, causal={causal})"
+        if prec == "fp64":
+            ref, _ = oracle_stream_scores(cube, B, S, pushes=blocks, causal=causal)
+            assert_scores(got, ref, B, 1e-9, 1e-11, label=f"served B={B} S={S} causal={causal}")
+        st.rx_destroy()
+    srv.rx_server_destroy()
