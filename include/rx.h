@@ -238,7 +238,8 @@ rx_status rx_destroy(rx_stream* s);
 const char* rx_last_error(void);
 
 /* Checkpoint/restore hooks.  rx_get_stats blocks, then writes the window
- * count, the mean [B] and the covariance M2/(N - ddof) [B][B] (row-major,
+ * count N (pixels in the statistics: finite pixels only for float input),
+ * the mean [B] and the covariance M2/(N - ddof) [B][B] (row-major,
  * full symmetric); mean and cov may be NULL.  rx_set_stats replaces the
  * window with (n, mean, cov): the scatter matrix becomes cov * (n - ddof). */
 rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double* cov);
