@@ -408,19 +408,32 @@ def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.
 
 def cpu_baseline(cube, budget_s):
     """The FP64 oracle as it stands, on the first blocks of the same cube, for
-    about budget_s seconds of CPU time (at least one block)."""
+    about budget_s seconds of CPU time (at least one block).  When a whole
+    pass over the 20 blocks fits, passes repeat (up to 3) while the budget
+    lasts and the median pass is reported."""
     from threadpoolctl import threadpool_info
     from oracle.stream import RxStreamOracle
-    o = RxStreamOracle(BANDS, SAMPLES, rho=RIDGE, block_lines=BLOCK, window_lines=LINES)
-    t0 = time.perf_counter()
-    outs = []
-    nb = 0
-    while nb < LINES // BLOCK:
-        outs.append(o.push(cube[nb * BLOCK:(nb + 1) * BLOCK]))
-        nb += 1
-        if time.perf_counter() - t0 > budget_s:
+    t_start = time.perf_counter()
+    outs, times = [], []
+    for rep in range(3):
+        o = RxStreamOracle(BANDS, SAMPLES, rho=RIDGE, block_lines=BLOCK, window_lines=LINES)
+        t0 = time.perf_counter()
+        nb = 0
+        while nb < LINES // BLOCK:
+            d = o.push(cube[nb * BLOCK:(nb + 1) * BLOCK])
+            if rep == 0:
+                outs.append(d)
+            nb += 1
+            if rep == 0 and time.perf_counter() - t0 > budget_s:
+                break
+        times.append(time.perf_counter() - t0)
+        if nb < LINES // BLOCK:
+            break                                  # a partial first pass: no repeats
+        spent = time.perf_counter() - t_start
+        if spent + times[0] > budget_s:
             break
-    dt = time.perf_counter() - t0
+    nb = sum(o.shape[0] for o in outs) // SAMPLES // BLOCK
+    dt = float(np.median(times))
     info = threadpool_info()
     threads = max([p.get("num_threads", 1) for p in info] or [1])
     blas = ", ".join(sorted({f"{p.get('internal_api')} {p.get('version')}" for p in info if p.get("user_api") == "blas"}))
@@ -428,8 +441,10 @@ def cpu_baseline(cube, budget_s):
     px = nb * BLOCK * SAMPLES
     return {"value": px / dt, "unit": "pixel-spectra/s", "cores": int(min(threads, cores)), "kind": "oracle",
             "affinity_cores": cores, "blas": blas or None,
+            "repetitions": len(times),
             "sample": f"first {nb} of 20 blocks ({nb * BLOCK} lines x {SAMPLES} x {BANDS}, exact integer "
-                      f"statistics + LU solves, ridge {RIDGE}), {dt:.1f} s"}, np.concatenate(outs)
+                      f"statistics + LU solves, ridge {RIDGE}), median of {len(times)} passes, {dt:.1f} s "
+                      f"per pass"}, np.concatenate(outs)
 
 
 def main():
@@ -437,7 +452,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="arrival window of the served-streams run (0 skips it)")
     ap.add_argument("--skip-fp64", action="store_true", help="skip the plain FP64 path (short profiling runs)")
