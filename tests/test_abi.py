@@ -66,3 +66,19 @@ def test_null_handles_are_rejected():
     assert rx.LIB.rx_scores(None, None, 0, C.byref(n), 0, None) == rx.RX_E_ARG
     assert rx.LIB.rx_init(None, None, None) == rx.RX_E_ARG
     assert rx.LIB.rx_server_destroy(None) == rx.RX_OK
+
+
+def test_footprint_accounts_for_causal_slot_and_float_validity():
+    # Host logic only (no GPU): the admission footprint grows by the causal
+    # mode's extra snapshot slot and by the float-input validity buffers,
+    # and counters carry the non-finite and FP8 saturation fields.
+    import numpy as np
+    from paper_2602_13509_amd import rx
+    base = rx.stream_footprint(rx.make_config(270, 640, in_dtype=np.uint16), 100)
+    causal = rx.stream_footprint(rx.make_config(270, 640, in_dtype=np.uint16, causal=True), 100)
+    flt = rx.stream_footprint(rx.make_config(270, 640, in_dtype=np.float32), 100)
+    assert causal > base and flt > base
+    assert flt - base >= 2 * 100 * 640               # two parity sets of one validity byte per pixel
+    assert rx.make_config(16, 16, causal=True).flags == rx.RX_FLAG_CAUSAL
+    names = [f[0] for f in rx.rx_counters._fields_]
+    assert names[-2:] == ["nonfinite_px", "fp8_saturated"]
