@@ -373,8 +373,9 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
 // Causal mode 2: slot nblk (the window before the batch, which scores block
 // 0) is the previous batch's last slot, already factored: copy what the
 // whitening reads (mean, operand or FP64 W, band and row scales, status) and
-// count block 0 as the factor counts the blocks it scores.  One workgroup
-// per batch; every size is a multiple of 16 bytes.
+// count block 0 as the factor counts the blocks it scores.  CPWG workgroups
+// per batch share the copies in 16-byte strides (every size is a multiple of
+// 16 bytes); the first one also moves the status.
 __global__ void __launch_bounds__(256) k_copy_slot(LaunchSet ls) {
   int z;
   const int bi = find_batch(ls, blockIdx.x, z);
@@ -383,14 +384,14 @@ __global__ void __launch_bounds__(256) k_copy_slot(LaunchSet ls) {
   auto copy = [&](void* dst, const void* src, int64_t bytes) {
     uint4* o = static_cast<uint4*>(dst);
     const uint4* i = static_cast<const uint4*>(src);
-    for (int64_t q = threadIdx.x; q < bytes / 16; q += 256) o[q] = i[q];
+    for (int64_t q = (int64_t)z * 256 + threadIdx.x; q < bytes / 16; q += CPWG * 256) o[q] = i[q];
   };
   copy(d.mu_snap + (int64_t)n * Bp, d.src_mu, (int64_t)Bp * 8);
   if (d.wl_bytes > 0) copy(static_cast<char*>(d.wlp) + n * d.wl_bytes, d.src_wlp, d.wl_bytes);
   else copy(d.w64 + (int64_t)n * Bp * Bp, d.src_w64, (int64_t)Bp * Bp * 8);
   copy(d.iscale + (int64_t)n * Bp, d.src_isc, (int64_t)Bp * 4);
   copy(d.oscale + (int64_t)n * Bp, d.src_osc, (int64_t)Bp * 4);
-  if (threadIdx.x == 0) {
+  if (z == 0 && threadIdx.x == 0) {
     const int st = d.src_status[0];
     d.status[n] = st;
     d.clipflag[n] = 0;
@@ -402,9 +403,10 @@ __global__ void __launch_bounds__(256) k_copy_slot(LaunchSet ls) {
 
 }  // namespace rxk
 
+// ls->wg0 must hold the prefix of CPWG workgroups per batch.
 extern "C" hipError_t rxk_launch_copy_slot(const rxk::LaunchSet* ls, int nb, hipStream_t st) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(rxk::k_copy_slot, dim3(nb), dim3(256), 0, st, *ls);
+  hipLaunchKernelGGL(rxk::k_copy_slot, dim3(nb * rxk::CPWG), dim3(256), 0, st, *ls);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ constexpr int MAXT = 20;      // max 16-band tiles: B <= 320
 constexpr int KC = 64;        // pixels per chunk (one line segment)
 constexpr int MAXB = 8;       // batches per launch (kernel-argument descriptors)
 constexpr int NT = 256;       // threads per workgroup of the streaming kernels
+constexpr int CPWG = 32;      // workgroups per batch of the snapshot-slot copy (causal mode)
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;

@@ -739,7 +739,7 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
       if (j.copy) {
         if (cs.nb == MAXB) return fail(RX_E_STATE, "too many batches in one launch");
         cs.d[cs.nb] = j.d;
-        cs.wg0[cs.nb + 1] = cs.nb + 1;
+        cs.wg0[cs.nb + 1] = CPWG * (cs.nb + 1);   // k_copy_slot: CPWG workgroups per batch
         ++cs.nb;
       }
     if (cs.nb > 0) {
