@@ -728,25 +728,6 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
   const bool piped = qs.A != qs.C;
   rx_stream* ps = piped ? jobs[0].s : nullptr;
   if (piped && jobs.size() != 1) return fail(RX_E_STATE, "pipelined launch of several jobs");
-  {
-    // causal batches whose window-before slot is the previous batch's last
-    // one: copy it on the whitening queue once the previous factorisation
-    // (the latest ev_fact) is done; this batch's merge and factor skip it
-    LaunchSet cs;
-    cs.nb = 0;
-    cs.wg0[0] = 0;
-    for (const Job& j : jobs)
-      if (j.copy) {
-        if (cs.nb == MAXB) return fail(RX_E_STATE, "too many batches in one launch");
-        cs.d[cs.nb] = j.d;
-        cs.wg0[cs.nb + 1] = CPWG * (cs.nb + 1);   // k_copy_slot: CPWG workgroups per batch
-        ++cs.nb;
-      }
-    if (cs.nb > 0) {
-      if (piped) HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
-      HIPC(rxk_launch_copy_slot(&cs, cs.nb, qs.C));
-    }
-  }
   auto run_groups = [&](auto key, auto launch) -> rx_status {
     std::vector<bool> done(jobs.size(), false);
     for (size_t a = 0; a < jobs.size(); ++a) {
@@ -772,6 +753,49 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
     }
     return ls.wg0[ls.nb];
   };
+  {
+    // causal batches whose window-before slot is the previous batch's last
+    // one: copy it on the whitening queue once the previous factorisation
+    // (the latest ev_fact) is done; this batch's merge and factor skip it
+    LaunchSet cs;
+    cs.nb = 0;
+    cs.wg0[0] = 0;
+    for (const Job& j : jobs)
+      if (j.copy) {
+        if (cs.nb == MAXB) return fail(RX_E_STATE, "too many batches in one launch");
+        cs.d[cs.nb] = j.d;
+        cs.wg0[cs.nb + 1] = CPWG * (cs.nb + 1);   // k_copy_slot: CPWG workgroups per batch
+        ++cs.nb;
+      }
+    if (cs.nb > 0) {
+      if (piped) HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+      HIPC(rxk_launch_copy_slot(&cs, cs.nb, qs.C));
+    }
+  }
+  auto whiten_all = [&]() -> rx_status {
+    rx_status r = run_groups([](const Job& j) { return (j.in_type * 16 + j.wp) * 1024 + j.Bw; },
+                             [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
+                               LaunchSet a;
+                               const int n = fill(a, grp, g0, g1, &Job::wg_whiten);
+                               rx_status q;
+                               if ((q = prof_mark(prof, 4, true, qs.C)) != RX_OK) return q;
+                               HIPC(rxk_launch_whiten(jobs[grp[g0]].in_type, jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw,
+                                                      qs.C));
+                               return prof_mark(prof, 4, false, qs.C);
+                             });
+    if (r != RX_OK) return r;
+    if (piped) HIPC(hipEventRecord(ps->ev_white[jobs[0].par], qs.C));
+    return RX_OK;
+  };
+  // a one-block causal batch whitens with the copied slot only: it needs the
+  // input, not this batch's statistics, so it is queued first (its scores do
+  // not wait behind the host time of the statistics launches)
+  const bool early = piped && jobs[0].fast;
+  if (early) {
+    HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
+    rx_status r0 = whiten_all();
+    if (r0 != RX_OK) return r0;
+  }
   rx_status r = run_groups([](const Job& j) { return j.in_type * 16 + j.sp; },
                            [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
                              LaunchSet a, b, c, e;
@@ -823,23 +847,9 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
   if (r != RX_OK) return r;
   if (piped) {
     HIPC(hipEventRecord(ps->ev_fact, qs.B));
-    // a one-block causal batch whitens with the copied slot only: it needs
-    // the input, not this batch's statistics
-    if (jobs[0].fast) HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
-    else HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+    if (!early) HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
   }
-  r = run_groups([](const Job& j) { return (j.in_type * 16 + j.wp) * 1024 + j.Bw; },
-                 [&](const std::vector<size_t>& grp, size_t g0, size_t g1) -> rx_status {
-                   LaunchSet a;
-                   const int n = fill(a, grp, g0, g1, &Job::wg_whiten);
-                   rx_status q;
-                   if ((q = prof_mark(prof, 4, true, qs.C)) != RX_OK) return q;
-                   HIPC(rxk_launch_whiten(jobs[grp[g0]].in_type, jobs[grp[g0]].wp, &a, n, jobs[grp[g0]].Bw, qs.C));
-                   return prof_mark(prof, 4, false, qs.C);
-                 });
-  if (r != RX_OK) return r;
-  if (piped) HIPC(hipEventRecord(ps->ev_white[jobs[0].par], qs.C));
-  return RX_OK;
+  return early ? RX_OK : whiten_all();
 }
 
 // ---------------------------------------------------------------------------- push
