@@ -117,3 +117,38 @@ def test_causal_one_block_pushes(rxm, prec):
     assert ca.notready_blocks == cb.notready_blocks == o.status.count("notready") == 2
     if prec != "fp8":
         assert_scores(a, ref, B, *TOL[prec], label=f"causal one-block pushes {prec}")
+
+
+def test_causal_after_set_stats_forms_the_slot_itself(rxm):
+    # A checkpoint restored with rx_set_stats invalidates the copied slot: the
+    # next causal push must score against the restored window (slot formed in
+    # the batch).  Stream A pushes lines 0..15 then 16..31; stream B restores
+    # A's statistics after line 15 and pushes 16..31: same scores on the FP64
+    # path (up to the restore's rounding of mean * n and cov * n).
+    L, B, S = 32, 40, 96
+    cube = synth.sensor_cube(34, lines=L, samples=S, bands=B).cube
+    x = dev(cube)
+    mk = lambda: rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten="fp64",
+                                              block_lines=8, causal=True))
+    a = mk()
+    a.rx_push_lines(x[:16])
+    a.rx_sync()
+    n, mean, cov = a.rx_get_stats()
+    a.scores_host(f64=True)
+    a.rx_push_lines(x[16:])
+    a.rx_sync()
+    want = a.scores_host(f64=True)
+    b = mk()
+    b.rx_push_lines(x[:8])                 # a push first, so a copied slot would exist
+    b.rx_sync()
+    b.scores_host(f64=True)
+    b.rx_set_stats(n, mean, cov)
+    b.rx_push_lines(x[16:])
+    b.rx_sync()
+    got = b.scores_host(f64=True)
+    assert n == 16 * S
+    assert_scores(got, want, B, 1e-9, 1e-11, label="causal after rx_set_stats")
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=8, causal=True, pushes=[16, 16])
+    assert_scores(got, ref[16 * S:], B, 1e-9, 1e-11, label="causal after rx_set_stats vs oracle")
+    a.rx_destroy()
+    b.rx_destroy()
