@@ -730,47 +730,49 @@ __global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
   if (k == 0) d.s1_out[d.Bp] = N;
 }
 
-// Matrix part: one workgroup per quarter of a lower 16x16 tile (4 rows x 16
-// columns, one entry per lane).  The four waves share out the blocks:
+// Matrix part, by row strips: a workgroup owns 4 consecutive rows and 64
+// consecutive columns at or below the diagonal; wave w takes row 4g + w and
+// lane l column 64c + l, so every load of a split partial is one contiguous
+// 256-byte row segment.  Each wave runs all blocks for its 64 entries:
 // C_b = fixed-order FP64 sum of the split partials, M2_b = C_b - n_b e e^T
-// (exact shift correction), into LDS; then one wave runs the pairwise
-// update M2 <- M2 + M2_b + w d d^T (or M2 <- M2_b for an empty window; M2
-// unchanged for a block with no finite pixel),
-// snapshotting the window's scatter matrix after every block.
+// (exact shift correction), then the pairwise update M2 <- M2 + M2_b +
+// w d d^T (M2 <- M2_b for an empty window; M2 unchanged for a block with no
+// finite pixel), snapshotting the window's scatter matrix after every block.
+// (Fewer, fuller workgroups than one per tile quarter: they leave more of the
+// GPU to the whitening running beside them.)
 template <typename PT>
 __global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
   int q;
   const int bi = find_batch(ls, blockIdx.x, q);
   const BatchDesc& d = ls.d[bi];
-  __shared__ double mbl[MAXBLK][MB];
-  const int lane = threadIdx.x & (MB - 1), w = threadIdx.x / MB;
-  const int t = q >> 2;
-  int ti = 0;
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  const int tj = t - ti * (ti + 1) / 2;
-  const int gi = 16 * ti + 4 * (q & 3) + (lane >> 4), gj = 16 * tj + (lane & 15);
-  const bool live = gi < d.B && gj < d.B && gi >= gj;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int g = 0;                                       // row group: columns 0 .. 4g + 3 in 64-wide chunks
+  while (q >= (4 * g + 67) / 64) { q -= (4 * g + 67) / 64; ++g; }
+  const int gi = 4 * g + w, gj = 64 * q + lane;
+  if (!(gi < d.B && gj <= gi)) return;
   const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
-  if (live) {
-    for (int b = w; b < d.nblk; b += MW) {
-      const double nb = d.nbv[b];
-      const int ksb = ks_of(d, b);
-      const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
-      double c = 0.0;
-      for (int s = 0; s < ksb; ++s) c += (double)pb[s * bp2];
-      const int64_t o = (int64_t)b * d.Bp;
-      mbl[b][lane] = c - nb * d.ev[o + gi] * d.ev[o + gj];
-    }
-  }
-  __syncthreads();
-  if (w != 0 || !live) return;
   double m2 = d.m2_in[e];
   if (d.causal == 1) d.m2_snap[d.nblk * bp2 + e] = (d.reset_bits & 1ull) ? 0.0 : m2;   // window before the batch
   for (int b = 0; b < d.nblk; ++b) {
-    if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
+    const double nb = d.nbv[b];
+    const int ksb = ks_of(d, b);
+    const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
+    double c = 0.0;
+    int sp = 0;
+    for (; sp + 4 <= ksb; sp += 4) {             // four loads in flight, summed in order
+      const double a0 = (double)pb[sp * bp2], a1 = (double)pb[(sp + 1) * bp2];
+      const double a2 = (double)pb[(sp + 2) * bp2], a3 = (double)pb[(sp + 3) * bp2];
+      c += a0;
+      c += a1;
+      c += a2;
+      c += a3;
+    }
+    for (; sp < ksb; ++sp) c += (double)pb[sp * bp2];
     const int64_t o = (int64_t)b * d.Bp;
+    const double mb = c - nb * d.ev[o + gi] * d.ev[o + gj];
+    if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
     const double wgt = d.coef[b];
-    if (wgt >= 0.0) m2 = (wgt > 0.0) ? m2 + mbl[b][lane] + wgt * d.dv[o + gi] * d.dv[o + gj] : mbl[b][lane];
+    if (wgt >= 0.0) m2 = (wgt > 0.0) ? m2 + mb + wgt * d.dv[o + gi] * d.dv[o + gj] : mb;
     d.m2_snap[b * bp2 + e] = m2;
   }
   d.m2_out[e] = m2;

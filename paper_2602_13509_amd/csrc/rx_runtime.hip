@@ -657,7 +657,8 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.wg_shift = nblk * (s->Bp / 4);
   j.wg_syrk = (whole_triangle(s->sp) ? 1 : d.nsup) * ((nblk - 1) * d.ks + d.ks_last);
   j.wg_merge = ceil_div(s->Bp, 64);
-  j.wg_mmat = 4 * (s->Bp / 16) * (s->Bp / 16 + 1) / 2;
+  j.wg_mmat = 0;                            // merge, matrix part: row strips of 4 x 64 entries
+  for (int g = 0; g < s->Bp / 4; ++g) j.wg_mmat += (4 * g + 67) / 64;
   j.wg_factor = nblk + (d.causal == 1 ? 1 : 0);   // causal, slot formed here: also the window before the batch
   j.wg_whiten = (int)(lines * s->cpl);
 
