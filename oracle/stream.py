@@ -141,11 +141,58 @@ def float_stats_chunked(chunks, ddof: int = 0):
     return n, mu, m2 / (n - ddof)
 
 
-def error_model_sd(px: np.ndarray, mu: np.ndarray, cov_r: np.ndarray, unit_roundoff: float):
+# Operand formats of the low-precision products: (significand bits p,
+# including the implicit one; exponent of the smallest normal).  Unit
+# roundoff u = 2^-p: 2^-8 for BF16, 2^-11 for FP16, 2^-4 for OCP FP8 E4M3.
+FORMATS = {"bf16": (8, -126), "fp16": (11, -14), "fp8": (4, -6)}
+
+
+def rounding_spacing(v: np.ndarray, fmt: str) -> np.ndarray:
+    """Gap between adjacent values of the format around v (the unit in the
+    last place): 2^(floor(log2|v|) + 1 - p) in the normal range, the fixed
+    subnormal gap 2^(emin + 1 - p) below it."""
+    p, emin = FORMATS[fmt]
+    a = np.abs(np.asarray(v, dtype=np.float64))
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, emin)
+    return np.ldexp(1.0, (e + 1 - p).astype(np.int64))
+
+
+def error_model_sd(px: np.ndarray, mu: np.ndarray, cov_r: np.ndarray, fmt: str, band_scale=None):
     """First-order standard deviation of the score error caused by rounding
-    each centred input value to a format of unit roundoff u before the
-    whitening product:  sd ~= (2u/sqrt(3)) * sqrt(sum_k d_k^2 (Sigma^-1 d)_k^2).
-    A reported estimate only (parity unpinned: nothing asserts against it)."""
-    d = np.asarray(px, dtype=np.float64) - mu[None, :]
+    each centred input value d_k = x_k - mu_k to the operand format before
+    the whitening product (the input-rounding term of the precision design;
+    the score is Eq. 1, Section "System Implementation / Detection
+    Algorithm").
+
+    Linearised: delta(d + e) - delta(d) ~= 2 z^T e with z = Sigma_r^{-1} d.
+    Round to nearest leaves an error spread evenly over one gap g_k of the
+    format around the value, variance g_k^2 / 12, independently per band, so
+
+        sd = 2 sqrt( sum_k z_k^2 g_k^2 / 12 ).
+
+    band_scale (optional, powers of two): the values are rounded as
+    d_k * band_scale_k (which moves them within the format's range; FP8's
+    subnormals depend on it) and scaled back.  With relative error taken as
+    uniform in [-u, u] instead, the same sum gives the cruder envelope
+    (2u / sqrt 3) sqrt(sum_k d_k^2 z_k^2).  A model of the input rounding
+    only: rounding of the whitening operand and of the covariance product
+    adds to the measured error."""
+    d = np.asarray(px, dtype=np.float64) - np.asarray(mu, dtype=np.float64)[None, :]
+    s = np.ones(d.shape[1]) if band_scale is None else np.asarray(band_scale, dtype=np.float64)
+    g = rounding_spacing(d * s[None, :], fmt) / s[None, :]
     z = np.linalg.solve(cov_r, d.T).T
-    return (2.0 * unit_roundoff / np.sqrt(3.0)) * np.sqrt(np.sum(d * d * z * z, axis=1))
+    return 2.0 * np.sqrt(np.sum(z * z * g * g, axis=1) / 12.0)
+
+
+def error_model_bias(px: np.ndarray, mu: np.ndarray, cov_r: np.ndarray, fmt: str, band_scale=None):
+    """Second-order mean of the same score error: the rounding error e also
+    enters the score as e^T Sigma_r^{-1} e, which is never negative; with the
+    errors independent and centred its expectation is
+    sum_k (Sigma_r^{-1})_kk g_k^2 / 12.  Small beside error_model_sd for BF16
+    and FP16; for FP8 E4M3 (u = 2^-4) it is a few tenths of it."""
+    d = np.asarray(px, dtype=np.float64) - np.asarray(mu, dtype=np.float64)[None, :]
+    s = np.ones(d.shape[1]) if band_scale is None else np.asarray(band_scale, dtype=np.float64)
+    g = rounding_spacing(d * s[None, :], fmt) / s[None, :]
+    dinv = np.diag(np.linalg.inv(cov_r))
+    return np.sum(dinv[None, :] * g * g, axis=1) / 12.0
