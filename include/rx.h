@@ -118,11 +118,16 @@ typedef struct rx_counters {
  * cumulative window, no ridge, device 0.  RX_E_ARG on a null cfg. */
 rx_status rx_config_init(rx_config* cfg, int32_t bands, int32_t samples);
 
-/* Create a stream.  server may be NULL (stand-alone stream); otherwise the
- * stream is admitted by the server's HBM budget (RX_E_BUDGET if it does not
- * fit or every slot is taken).  Allocates the stream's resident state
- * (window mean and scatter matrix in FP64) on cfg->device.  *out receives
- * the handle (NULL on failure). */
+/* Create a stream: one push-broom sensor whose lines arrive continuously
+ * (paper, Section "System Architecture / Data Acquisition") and whose
+ * statistics window starts empty (Section "System Implementation / Detection
+ * Algorithm": mean and covariance over the set of pixels).  server may be
+ * NULL (stand-alone stream); otherwise the stream is admitted by the
+ * server's HBM budget (RX_E_BUDGET if it does not fit or every slot is
+ * taken).  Allocates the stream's resident state (window band sums and
+ * scatter matrix in FP64) on cfg->device.  *out receives the handle (NULL on
+ * failure); RX_E_ARG for a bad config, RX_E_NOMEM / RX_E_DEVICE when the
+ * device refuses. */
 rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
 
 /* Push n_lines >= 1 lines, BIL [n_lines][B][S] of cfg->in_type, contiguous.
@@ -144,7 +149,10 @@ rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
 rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_lines, int32_t is_device_ptr,
                         void* hip_stream);
 
-/* Pop up to max_px of the oldest pending scores (FP32) into out.
+/* Pop up to max_px of the oldest pending scores (FP32) into out: the
+ * per-pixel RX score delta of Eq. 1 (paper, Section "System Implementation /
+ * Detection Algorithm"), in FP32 as the paper's ground station receives it
+ * (Section "System Implementation / Data Transmission").
  * out_is_device = 0: host buffer, the call blocks until they are written.
  * out_is_device = 1: device buffer on cfg->device, written asynchronously
  * after the work already queued on hip_stream (which may still be using the
@@ -230,8 +238,13 @@ rx_status rx_sync(rx_stream* s);
 /* Counters (blocks the host, like rx_sync, without clearing errors). */
 rx_status rx_get_counters(rx_stream* s, rx_counters* out);
 
-/* Destroy a stream: waits for its work, frees its device memory, and
- * releases its server admission.  NULL is accepted (no-op). */
+/* Destroy a stream: its statistics window ends with it, as a cube's
+ * distribution serves only that cube's pixels (paper, Section "System
+ * Implementation / Detection Algorithm": each cube is an independent
+ * entity).  Waits for its work, frees its device memory, and releases its
+ * server admission (the HBM it was charged returns to the budget).  NULL is
+ * accepted (no-op); RX_E_STATE for a handle that is not live (already
+ * destroyed). */
 rx_status rx_destroy(rx_stream* s);
 
 /* Thread-local message for the last non-OK status on this thread. */
@@ -253,6 +266,17 @@ rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, const double
  * last rx_profile call (which also resets them). */
 rx_status rx_profile(rx_stream* s, int32_t enable);
 rx_status rx_phase_times(rx_stream* s, double* ms, int64_t* launches);
+
+/* Test hook (host only, no device work): how the covariance product of a
+ * block of `lines` lines under cfg is cut into splits (independent partial
+ * products summed in a fixed order, Section "System Implementation /
+ * Detection Algorithm": the covariance over the block's pixels).
+ * *splits = the number of splits, *max_chunks = the most 64-sample line
+ * chunks one split holds.  For 16-bit input each split's exact raw band sums
+ * are 32-bit per thread, 8 values per chunk: the plan keeps
+ * 8 * 65535 * max_chunks < 2^32 for any block length.  RX_E_ARG for a bad
+ * config, lines outside [1, 2^31 - 1] or a null output. */
+rx_status rx_split_plan(const rx_config* cfg, int64_t lines, int32_t* splits, int64_t* max_chunks);
 
 /* Test hook: the FP64 whitening factor W (lower triangular, [B][B]
  * row-major, W^T W = (Sigma + lambda I)^{-1}) of the most recent block. */

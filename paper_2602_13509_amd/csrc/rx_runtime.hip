@@ -67,13 +67,18 @@ struct DevBuf {
   size_t cap = 0;
 };
 
-static rx_status dev_ensure(DevBuf& b, size_t bytes, hipStream_t st) {
+struct rx_stream;
+static hipError_t sync_all(rx_stream* s);
+
+// Grow a buffer owned by stream `owner` (NULL: nothing can be using it).
+// Growing is rare (first push, a larger batch); the old buffer may still be
+// read by work queued on any of the owner's queues (a served stream's queue is
+// its server's), so those queues are drained first -- not the whole device,
+// which would stall every other stream.
+static rx_status dev_ensure(DevBuf& b, size_t bytes, rx_stream* owner) {
   if (bytes <= b.cap) return RX_OK;
   if (b.p) {
-    // growing is rare (first push, larger batch); the old buffer may still be
-    // read on any of the stream's queues, so wait for the whole device
-    (void)st;
-    HIPC(hipDeviceSynchronize());
+    if (owner) HIPC(sync_all(owner));
     HIPC(hipFree(b.p));
     b.p = nullptr;
     b.cap = 0;
@@ -110,9 +115,17 @@ static size_t in_elem_size(int t) { return t == RX_IN_U16 ? 2 : (t == RX_IN_F32 
 // Splits depend only on the block (never on the batch), so a block's result
 // is the same alone and in any batch.
 static bool whole_triangle(int sp) { return sp == RX_BF16 || sp == RX_FP16; }
-static int splits_for(int lines, int cpl, int sp) {
+// The covariance kernels keep each split's raw band sums of 16-bit input as
+// exact uint32 per thread, and a thread adds 8 values of at most 65535 per
+// chunk: a split of at most kMaxChunksPerSplit chunks cannot wrap
+// (8 * 65535 * 8192 = 4 294 901 760 < 2^32).  Splits are capped at 64 per
+// block unless a block is so long that 64 would exceed that.
+static constexpr int64_t kMaxChunksPerSplit = 8192;
+static int splits_for(int64_t lines, int cpl, int sp) {
   const int per = whole_triangle(sp) ? kSplitChunks2 : kSplitChunks;
-  return std::min(64, std::max(1, ceil_div((int64_t)lines * cpl, per)));
+  const int64_t nch = lines * cpl;
+  const int64_t cap = std::max<int64_t>(64, (nch + kMaxChunksPerSplit - 1) / kMaxChunksPerSplit);
+  return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (nch + per - 1) / per));
 }
 
 // Rectangles of at most 4 x 4 16-band tiles covering the lower triangle of
@@ -249,11 +262,16 @@ struct rx_stream {
   int64_t prof_n[5] = {0, 0, 0, 0, 0};
   rx_counters cnt{};
   rx_status sticky = RX_OK;
+  // a launch failed after the stream's state had advanced: its statistics and
+  // FIFO no longer match what was launched, so every later call refuses
+  bool broken = false;
+  int64_t q_lines = 0;                    // served: lines submitted and not yet launched
 };
 
 static rx_status check_stream(rx_stream* s) {
   if (!s) return fail(RX_E_ARG, "null stream");
   if (s->magic != kMagic) return fail(RX_E_STATE, "stream handle is not live");
+  if (s->broken) return fail(RX_E_STATE, "a launch on this stream failed earlier; destroy it");
   return RX_OK;
 }
 
@@ -332,6 +350,18 @@ extern "C" rx_status rx_stream_footprint(const rx_config* cfg, int32_t max_block
   return RX_OK;
 }
 
+extern "C" rx_status rx_split_plan(const rx_config* cfg, int64_t lines, int32_t* splits, int64_t* max_chunks) {
+  rx_status r = validate(cfg);
+  if (r != RX_OK) return r;
+  if (lines < 1 || lines > INT32_MAX || !splits || !max_chunks) return fail(RX_E_ARG, "bad block or null output");
+  const int cpl = ceil_div(cfg->samples, KC);
+  const int ks = splits_for(lines, cpl, cfg->syrk_prec);
+  const int64_t nch = lines * cpl;
+  *splits = ks;
+  *max_chunks = (nch + ks - 1) / ks;       // split s holds chunks [nch s / ks, nch (s + 1) / ks)
+  return RX_OK;
+}
+
 // ---------------------------------------------------------------------------- init / destroy
 // Wait for every queue of a stream (A and B feed C, but host reads of the
 // statistics, counters or W must not depend on that).
@@ -370,26 +400,26 @@ static void free_stream(rx_stream* s) {
 static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   const Sizes z = scratch_sizes(s->B, s->S, s->in_type, s->sp, nblk, blk_lines);
   rx_status r;
-  if ((r = dev_ensure(s->shift, z.shift, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->part, z.part, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->psum, z.psum, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->shift, z.shift, s)) != RX_OK) return r;
+  if ((r = dev_ensure(s->part, z.part, s)) != RX_OK) return r;
+  if ((r = dev_ensure(s->psum, z.psum, s)) != RX_OK) return r;
   bool zeroed = false;
   for (int q = 0; q < s->npar; ++q) {
-    if ((r = dev_ensure(s->m2s[q], z.m2, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->nsnap[q], z.nsnap, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->mu[q], z.mu, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->m2s[q], z.m2, s)) != RX_OK) return r;
+    if ((r = dev_ensure(s->nsnap[q], z.nsnap, s)) != RX_OK) return r;
+    if ((r = dev_ensure(s->mu[q], z.mu, s)) != RX_OK) return r;
     // the factor never writes above the diagonal tiles of W or its
     // low-precision copy (nor the copy's padding columns): those stay as
     // zeroed here
     const size_t w_before = s->w64[q].cap, wl_before = s->wlp[q].cap;
-    if ((r = dev_ensure(s->w64[q], z.w64, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->wlp[q], z.wlp, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->w64[q], z.w64, s)) != RX_OK) return r;
+    if ((r = dev_ensure(s->wlp[q], z.wlp, s)) != RX_OK) return r;
     if (s->w64[q].cap != w_before) { HIPC(hipMemsetAsync(s->w64[q].p, 0, s->w64[q].cap, s->st)); zeroed = true; }
     if (s->wlp[q].cap != wl_before) { HIPC(hipMemsetAsync(s->wlp[q].p, 0, s->wlp[q].cap, s->st)); zeroed = true; }
-    if ((r = dev_ensure(s->isc[q], z.scl, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->osc[q], z.scl, s->st)) != RX_OK) return r;
-    if ((r = dev_ensure(s->status[q], z.status, s->st)) != RX_OK) return r;
-    if (z.valid && (r = dev_ensure(s->valid[q], z.valid, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->isc[q], z.scl, s)) != RX_OK) return r;
+    if ((r = dev_ensure(s->osc[q], z.scl, s)) != RX_OK) return r;
+    if ((r = dev_ensure(s->status[q], z.status, s)) != RX_OK) return r;
+    if (z.valid && (r = dev_ensure(s->valid[q], z.valid, s)) != RX_OK) return r;
   }
   // buffers zeroed on queue C must be clear before queue B's factor writes
   // them (only after a growth: otherwise B must not wait behind C)
@@ -397,11 +427,11 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
     HIPC(hipEventRecord(s->ev_done, s->st));
     HIPC(hipStreamWaitEvent(s->stB, s->ev_done, 0));
   }
-  if ((r = dev_ensure(s->evb, z.ev, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->dvb, z.ev, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->coefb, z.coef, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->nbvb, z.coef, s->st)) != RX_OK) return r;
-  if (z.nbadl && (r = dev_ensure(s->nbadl, z.nbadl, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->evb, z.ev, s)) != RX_OK) return r;
+  if ((r = dev_ensure(s->dvb, z.ev, s)) != RX_OK) return r;
+  if ((r = dev_ensure(s->coefb, z.coef, s)) != RX_OK) return r;
+  if ((r = dev_ensure(s->nbvb, z.coef, s)) != RX_OK) return r;
+  if (z.nbadl && (r = dev_ensure(s->nbadl, z.nbadl, s)) != RX_OK) return r;
   return RX_OK;
 }
 
@@ -468,17 +498,17 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
   const size_t s1b = (size_t)(s->Bp + 1) * 8, m2b = (size_t)s->Bp * s->Bp * 8;
   for (int i = 0; i < 2; ++i) {
-    if ((r = dev_ensure(s->s1[i], s1b, s->st)) != RX_OK) return bail(r);
-    if ((r = dev_ensure(s->m2[i], m2b, s->st)) != RX_OK) return bail(r);
+    if ((r = dev_ensure(s->s1[i], s1b, s)) != RX_OK) return bail(r);
+    if ((r = dev_ensure(s->m2[i], m2b, s)) != RX_OK) return bail(r);
     if (hipMemsetAsync(s->s1[i].p, 0, s1b, s->st) != hipSuccess || hipMemsetAsync(s->m2[i].p, 0, m2b, s->st) != hipSuccess)
       return bail(fail(RX_E_DEVICE, "hipMemsetAsync failed"));
   }
-  if ((r = dev_ensure(s->nsing, 256, s->st)) != RX_OK) return bail(r);
+  if ((r = dev_ensure(s->nsing, 256, s)) != RX_OK) return bail(r);
   if (hipMemsetAsync(s->nsing.p, 0, 256, s->st) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipMemsetAsync failed"));
   if (s->srv) {
     const int mbl = cfg->block_lines > 0 ? cfg->block_lines : 128;
     if ((r = alloc_scratch(s, 1, mbl)) != RX_OK) return bail(r);
-    if ((r = dev_ensure(s->pend[0], (size_t)2 * mbl * s->S * (s->sc_f64 ? 8 : 4), s->st)) != RX_OK) return bail(r);
+    if ((r = dev_ensure(s->pend[0], (size_t)2 * mbl * s->S * (s->sc_f64 ? 8 : 4), s)) != RX_OK) return bail(r);
   }
   if (hipStreamSynchronize(s->st) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipStreamSynchronize failed"));
   *out = s;
@@ -487,8 +517,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
 
 extern "C" rx_status rx_destroy(rx_stream* s) {
   if (!s) return RX_OK;
-  rx_status r = check_stream(s);
-  if (r != RX_OK) return r;
+  if (s->magic != kMagic) return fail(RX_E_STATE, "stream handle is not live");
   (void)hipSetDevice(s->dev);
   (void)sync_all(s);
   if (s->srv) {
@@ -514,7 +543,7 @@ static rx_status pending_reserve(rx_stream* s, int64_t npx) {
   if ((size_t)(s->tail + npx) * es <= cur.cap) return RX_OK;
   DevBuf& alt = s->pend[1 - s->pcur];
   const size_t need = (size_t)(live + npx) * es;
-  rx_status r = dev_ensure(alt, std::max(need, cur.cap * 2), s->st);
+  rx_status r = dev_ensure(alt, std::max(need, cur.cap * 2), s);
   if (r != RX_OK) return r;
   if (live > 0)
     HIPC(hipMemcpyAsync(alt.p, static_cast<char*>(cur.p) + (size_t)s->head * es, (size_t)live * es,
@@ -548,29 +577,61 @@ static void cut_blocks(const rx_stream* s, int64_t pos, int64_t n_lines, std::ve
       take = std::min<int64_t>(take, R - (pos + off) % R);
       reset = ((pos + off) % R) == 0;
     }
-    out.push_back(Block{off, (int)take, reset});
+    out.push_back(Block{off, take > INT32_MAX ? 0 : (int)take, reset});
     off += take;
   }
 }
 
-// Fill a job for blocks[i0, i1) of a push whose lines start at x.  Updates
-// the host copy of N and the pending tail; reserves scratch.
+// Group a push's blocks into batches (launched together): runs of up to
+// kMaxBlocksPerBatch blocks of one length, plus one shorter block at the end.
+static std::vector<std::pair<size_t, size_t>> plan_batches(const std::vector<Block>& blks) {
+  std::vector<std::pair<size_t, size_t>> out;
+  size_t i = 0;
+  while (i < blks.size()) {
+    size_t k = i + 1;
+    while (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines == blks[i].lines) ++k;
+    if (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines < blks[i].lines) ++k;
+    out.push_back({i, k});
+    i = k;
+  }
+  return out;
+}
+
+// Everything the batches of a push (or of a server step) can allocate,
+// reserved before any stream state changes: scratch for each batch (buffers
+// only grow, so the largest need wins) and FIFO room for all their pixels.
+// A failure here leaves the stream's statistics, FIFO and parity untouched.
+static rx_status reserve_batches(rx_stream* s, const std::vector<Block>& blks,
+                                 const std::vector<std::pair<size_t, size_t>>& batches) {
+  const int pp = s->prev_par;
+  const DevBuf* kept[6] = {&s->mu[pp], &s->wlp[pp], &s->w64[pp], &s->isc[pp], &s->osc[pp], &s->status[pp]};
+  size_t cap0[6];
+  for (int i = 0; i < 6; ++i) cap0[i] = kept[i]->cap;
+  int64_t lines = 0;
+  for (const auto& bt : batches) {
+    rx_status r = alloc_scratch(s, (int)(bt.second - bt.first) + s->causal, blks[bt.first].lines);
+    if (r != RX_OK) return r;
+    for (size_t i = bt.first; i < bt.second; ++i) lines += blks[i].lines;
+  }
+  for (int i = 0; i < 6; ++i)
+    if (kept[i]->cap != cap0[i]) s->prev_valid = false;   // reallocated: the previous slot is gone
+  return pending_reserve(s, lines * s->S);
+}
+
+// Fill a job for blocks[i0, i1) of a push whose lines start at x (after
+// reserve_batches).  Updates the host copy of N, the pending tail and the
+// parity; cannot fail once the reservation is made.
 static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Block>& blks, size_t i0, size_t i1,
                              Job& j, bool& notready, bool allow_copy = false) {
   const int nblk = (int)(i1 - i0);
   const int L = blks[i0].lines, last = blks[i1 - 1].lines;
   const int pp = s->prev_par;
-  const DevBuf* kept[6] = {&s->mu[pp], &s->wlp[pp], &s->w64[pp], &s->isc[pp], &s->osc[pp], &s->status[pp]};
-  size_t cap0[6];
-  for (int i = 0; i < 6; ++i) cap0[i] = kept[i]->cap;
-  rx_status r = alloc_scratch(s, nblk + s->causal, L);
-  if (r != RX_OK) return r;
-  for (int i = 0; i < 6; ++i)
-    if (kept[i]->cap != cap0[i]) s->prev_valid = false;   // reallocated: the previous slot is gone
   int64_t lines = 0;
   for (size_t i = i0; i < i1; ++i) lines += blks[i].lines;
   const int64_t npx = lines * s->S;
-  if ((r = pending_reserve(s, npx)) != RX_OK) return r;
+  // reserve_batches has sized every buffer and the FIFO for this batch
+  if ((size_t)(s->tail + npx) * (s->sc_f64 ? 8 : 4) > s->pend[s->pcur].cap)
+    return fail(RX_E_STATE, "internal: batch prepared without a reservation");
 
   BatchDesc& d = j.d;
   std::memset(&d, 0, sizeof d);
@@ -874,7 +935,7 @@ static rx_status stage_host_input(rx_stream* s, const void* lines, size_t bytes,
     }
     s->host_pin_cap = bytes;
   }
-  rx_status r = dev_ensure(s->stage, bytes, s->st);
+  rx_status r = dev_ensure(s->stage, bytes, s);
   if (r != RX_OK) return r;
   std::memcpy(s->host_pin, lines, bytes);
   HIPC(hipMemcpyAsync(s->stage.p, s->host_pin, bytes, hipMemcpyHostToDevice, s->stA));
@@ -896,6 +957,11 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
   const void* x = lines;
   std::vector<Block> blks;
   cut_blocks(s, s->lines_seen, n_lines, blks);
+  for (const Block& bk : blks)
+    if (bk.lines < 1) return fail(RX_E_ARG, "a block exceeds %d lines; set block_lines", INT32_MAX);
+  // every allocation of the push happens here, before the stream changes
+  const auto batches = plan_batches(blks);
+  if ((r = reserve_batches(s, blks, batches)) != RX_OK) return r;
   // A one-block device push to an idle stream (every earlier push done) runs
   // on one queue: no cross-queue handoffs, the lowest latency for a lone
   // block.  Other pushes go over the three queues, so that consecutive
@@ -918,17 +984,13 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     HIPC(hipStreamWaitEvent(qs.A, s->ev_in, 0));     // queues B and C follow A by events
   }
   bool notready = false;
-  size_t i = 0;
-  while (i < blks.size()) {
-    size_t k = i + 1;
-    while (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines == blks[i].lines) ++k;
-    if (k < blks.size() && (int)(k - i) < kMaxBlocksPerBatch && blks[k].lines < blks[i].lines) ++k;
+  for (const auto& bt : batches) {
+    const size_t i = bt.first, k = bt.second;
     std::vector<Job> jobs(1);
-    if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready, true)) != RX_OK) return r;
+    if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready, true)) != RX_OK) { s->broken = true; return r; }
     // (float input: the whitening also reads the validity pass's output)
     jobs[0].fast = jobs[0].copy && k - i == 1 && is_device_ptr && !one_queue && s->in_type == RX_IN_U16;
-    if ((r = launch_jobs(jobs, qs, s)) != RX_OK) return r;
-    i = k;
+    if ((r = launch_jobs(jobs, qs, s)) != RX_OK) { s->broken = true; return r; }
   }
   if (!is_device_ptr) HIPC(hipEventRecord(s->ev_stage, s->st));   // last reader of the staging buffer
   HIPC(hipEventRecord(s->ev_last, s->st));
@@ -971,7 +1033,7 @@ static rx_status pop_scores(rx_stream* s, void* out, int want_f64, int64_t max_p
   const char* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * es;
   const void* from = src;
   if ((int)s->sc_f64 != want_f64) {
-    if ((r = dev_ensure(s->cvt, (size_t)n * eo, s->st)) != RX_OK) return r;
+    if ((r = dev_ensure(s->cvt, (size_t)n * eo, s)) != RX_OK) return r;
     const int g = ceil_div(n, 256);
     if (want_f64) hipLaunchKernelGGL(k_f32_to_f64, dim3(g), dim3(256), 0, s->st, (const float*)src, (double*)s->cvt.p, n);
     else hipLaunchKernelGGL(k_f64_to_f32, dim3(g), dim3(256), 0, s->st, (const double*)src, (float*)s->cvt.p, n);
@@ -1070,8 +1132,8 @@ extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, 
   if (n == 0) return RX_OK;
   if (!bits || max_bytes < nbytes) return fail(RX_E_ARG, "mask buffer needs %lld bytes", (long long)nbytes);
   const int64_t words = (n + 31) / 32;
-  if ((r = dev_ensure(s->maskbits, (size_t)words * 4, s->st)) != RX_OK) return r;
-  if ((r = dev_ensure(s->maskscr, 4096, s->st)) != RX_OK) return r;
+  if ((r = dev_ensure(s->maskbits, (size_t)words * 4, s)) != RX_OK) return r;
+  if ((r = dev_ensure(s->maskscr, 4096, s)) != RX_OK) return r;
   const void* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * (s->sc_f64 ? 8 : 4);
   if (mode == RX_THR_TOPK && k == 0) {
     HIPC(hipMemsetAsync(s->maskbits.p, 0, (size_t)words * 4, s->st));
@@ -1268,53 +1330,81 @@ extern "C" rx_status rx_server_submit(rx_server* srv, rx_stream* s, const void* 
   const int mbl = s->cfg.block_lines > 0 ? s->cfg.block_lines : 128;
   if (n_lines > mbl) return fail(RX_E_ARG, "block of %lld lines exceeds the stream's %d", (long long)n_lines, mbl);
   std::lock_guard<std::mutex> lk(srv->mu);
+  // the block starts where the stream's queued blocks end: it must end at or
+  // before the next window edge (refused here, so a step never meets it)
+  const int64_t R = s->cfg.window_lines, pos = s->lines_seen + s->q_lines;
+  if (R > 0 && pos % R + n_lines > R)
+    return fail(RX_E_ARG, "block of %lld lines at line %lld straddles a window edge (every %lld lines)",
+                (long long)n_lines, (long long)pos, (long long)R);
   srv->queue.push_back(Pending{s, lines_dev, n_lines, tag});
+  s->q_lines += n_lines;
   return RX_OK;
 }
 
 extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
   if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  if (n_blocks) *n_blocks = 0;
   HIPC(hipSetDevice(srv->dev));
   std::lock_guard<std::mutex> lk(srv->mu);
-  // one block per stream per step (a stream's blocks depend on each other)
-  std::vector<Pending> take;
-  for (auto it = srv->queue.begin(); it != srv->queue.end();) {
+  // one block per stream per step (a stream's blocks depend on each other):
+  // the oldest queued block of each stream, left in the queue until every
+  // allocation of the step has succeeded
+  std::vector<size_t> pick;
+  std::vector<std::vector<Block>> blks;
+  for (size_t q = 0; q < srv->queue.size(); ++q) {
     bool seen = false;
-    for (auto& t : take) seen |= (t.s == it->s);
-    if (!seen) {
-      take.push_back(*it);
-      it = srv->queue.erase(it);
-    } else {
-      ++it;
-    }
+    for (size_t t : pick) seen |= (srv->queue[t].s == srv->queue[q].s);
+    if (seen || srv->queue[q].s->broken) continue;
+    pick.push_back(q);
   }
-  if (n_blocks) *n_blocks = (int32_t)take.size();
-  if (take.empty()) return RX_OK;
+  if (pick.empty()) return RX_OK;
+  blks.resize(pick.size());
+  for (size_t i = 0; i < pick.size(); ++i) {
+    const Pending& pq = srv->queue[pick[i]];
+    cut_blocks(pq.s, pq.s->lines_seen, pq.lines, blks[i]);
+    if (blks[i].size() != 1) return fail(RX_E_STATE, "internal: a queued block straddles a window edge");
+  }
+  for (size_t i = 0; i < pick.size(); ++i) {
+    rx_status r = reserve_batches(srv->queue[pick[i]].s, blks[i], {{0, 1}});
+    if (r != RX_OK) return r;                 // nothing taken, no stream changed
+  }
+  // from here on the step is committed
+  std::vector<Pending> take;
+  for (size_t t : pick) take.push_back(srv->queue[t]);
+  for (size_t i = pick.size(); i-- > 0;) srv->queue.erase(srv->queue.begin() + (std::ptrdiff_t)pick[i]);
   std::vector<Job> jobs(take.size());
   InFlight f;
   for (size_t i = 0; i < take.size(); ++i) {
     rx_stream* s = take[i].s;
-    std::vector<Block> blks;
-    cut_blocks(s, s->lines_seen, take[i].lines, blks);
-    if (blks.size() != 1) return fail(RX_E_ARG, "a served block must not straddle a window edge");
     bool notready = false;
-    rx_status r = prepare_job(s, take[i].x, blks, 0, 1, jobs[i], notready);
-    if (r != RX_OK) return r;
+    rx_status r = prepare_job(s, take[i].x, blks[i], 0, 1, jobs[i], notready);
+    if (r != RX_OK) {
+      for (size_t k = 0; k <= i; ++k) take[k].s->broken = true;
+      return r;
+    }
     s->lines_seen += take[i].lines;
+    s->q_lines -= take[i].lines;
     s->cnt.lines_pushed += take[i].lines;
     f.items.push_back({s, take[i].tag});
   }
   rx_status r = launch_jobs(jobs, Queues{srv->st, srv->st, srv->st});
-  if (r != RX_OK) return r;
-  if (srv->free_events.empty()) {
+  if (r == RX_OK && srv->free_events.empty()) {
     hipEvent_t e;
-    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    srv->free_events.push_back(e);
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) r = fail(RX_E_DEVICE, "hipEventCreate failed");
+    else srv->free_events.push_back(e);
   }
-  f.ev = srv->free_events.back();
-  srv->free_events.pop_back();
-  HIPC(hipEventRecord(f.ev, srv->st));
+  if (r == RX_OK) {
+    f.ev = srv->free_events.back();
+    if (hipEventRecord(f.ev, srv->st) != hipSuccess) r = fail(RX_E_DEVICE, "hipEventRecord failed");
+    else srv->free_events.pop_back();
+  }
+  if (r != RX_OK) {
+    // the streams' state has advanced past blocks whose work did not launch
+    for (auto& t : take) t.s->broken = true;
+    return r;
+  }
   srv->inflight.push_back(std::move(f));
+  if (n_blocks) *n_blocks = (int32_t)take.size();
   return RX_OK;
 }
 

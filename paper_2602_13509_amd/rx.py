@@ -33,7 +33,7 @@ EXPORTED = [
     "rx_sync", "rx_get_counters", "rx_destroy", "rx_last_error", "rx_get_stats", "rx_set_stats",
     "rx_get_whitener", "rx_server_create", "rx_server_destroy", "rx_stream_footprint", "rx_server_submit",
     "rx_server_step", "rx_server_poll", "rx_server_sync", "rx_server_queued", "rx_profile",
-    "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode", "rx_bin_bands",
+    "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode", "rx_bin_bands", "rx_split_plan",
 ]
 
 
@@ -59,6 +59,16 @@ class RxError(RuntimeError):
 
 
 def _load():
+    # The library and PyTorch's ROCm build each need a HIP runtime under the
+    # same soname (libamdhip64.so.7); the dynamic loader gives the whole
+    # process whichever is loaded first.  Importing torch first keeps the
+    # process on the runtime torch was built with, which the library also
+    # runs on; the other order leaves torch on a runtime it was not built for
+    # and the first kernel launch finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950) first")
@@ -93,6 +103,7 @@ def _load():
         "rx_tx_decode": (I32, [P, I64, P, C.c_float, P, P, P]),
         "rx_encode": (I32, [P, P, I64, C.POINTER(I64), P, P]),
         "rx_bin_bands": (I32, [P, I64, I32, I32, I32, I32, I32, I32, P, P]),
+        "rx_split_plan": (I32, [C.POINTER(rx_config), I64, C.POINTER(I32), C.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -330,3 +341,11 @@ def bin_bands(cube, b0: int, nb: int, k: int, out, bit_depth: int = 12, stream=N
     lines, bands, samples = cube.shape
     check(LIB.rx_bin_bands(_ptr(cube), lines, bands, samples, b0, nb, k, bit_depth, _ptr(out),
                            _stream_handle(stream)))
+
+
+def split_plan(cfg: rx_config, lines: int):
+    """(splits, most chunks in one split) of the covariance product for a
+    block of `lines` lines under cfg (host-only query, no device work)."""
+    ks, mc = C.c_int32(0), C.c_int64(0)
+    check(LIB.rx_split_plan(C.byref(cfg), lines, C.byref(ks), C.byref(mc)))
+    return ks.value, mc.value

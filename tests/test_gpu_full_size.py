@@ -6,7 +6,10 @@
   takes exact integer moments of every block, forms each block's window
   statistics exactly, and scores a sample of each block's pixels with an LU
   solve.  FP64 path: tolerance of the FP64 scoring tests; BF16 path with the
-  1e-6 ridge: the BF16 tolerance (max 5e-2, p99 1e-2).
+  1e-6 ridge: the BF16 tolerance (max 5e-2, p99 1e-2).  Every pixel of the
+  same push is also scored by the oracle to check the BF16 path's masks
+  (absolute at the (1 - 5e-4) quantile, relative 0.110) bit for bit outside
+  the tolerance band around the threshold.
 * The 5000 x 1024 x 300 float32 stress cube (condition number 1e6, band
   range 1e3) as one block: FP64 statistics, then FP64 whitening (tolerance
   1e-7 / 1e-9) and FP16 / FP8 whitening, whose scores are checked against the
@@ -16,7 +19,7 @@ Both generate their cubes on the host (tens of seconds) and are marked slow.
 import numpy as np
 import pytest
 
-from gpu_util import assert_scores, err_summary, say
+from gpu_util import assert_mask, assert_scores, err_summary, oracle_stream_scores, say
 from oracle import rx as orx
 from oracle.stream import float_stats_chunked
 from paper_2602_13509_amd import synth
@@ -32,10 +35,15 @@ def rxm():
     return rx
 
 
-def test_sensor_cube_full_size_sampled(rxm):
+@pytest.fixture(scope="module")
+def sensor_full():
+    return synth.sensor_cube(0, lines=2000, samples=640, bands=270).cube
+
+
+def test_sensor_cube_full_size_sampled(rxm, sensor_full):
     import torch
     L, S, B, BL = 2000, 640, 270, 100
-    cube = synth.sensor_cube(0, lines=L, samples=S, bands=B).cube
+    cube = sensor_full
     x = torch.from_numpy(cube).cuda()
     got = {}
     for prec, rho in (("fp64", 0.0), ("bf16", 1e-6)):
@@ -65,6 +73,37 @@ def test_sensor_cube_full_size_sampled(rxm):
     say(f"sensor full size: {idx.size} sampled pixels over 20 blocks")
     assert_scores(got["fp64"][idx], np.concatenate(ref64), B, 1e-9, 1e-11, "sensor full fp64")
     assert_scores(got["bf16"][idx], np.concatenate(refbf), B, 5e-2, 1e-2, "sensor full bf16")
+
+
+def test_sensor_cube_full_size_bf16_masks(rxm, sensor_full):
+    # Mask agreement of the BF16 path (BF16 covariance and whitening, FP64
+    # factor, 1e-6 ridge) with the FP64 oracle (same ridge) over every pixel
+    # of the full sensor cube, pushed as the benchmark pushes it.  Absolute
+    # threshold at the oracle's (1 - 5e-4) quantile of the cube's scores;
+    # relative threshold 0.110 of the cube's maximum (the value the paper's
+    # flights use).  The masks must agree bit for bit wherever the oracle
+    # score is farther from the threshold than the BF16 tolerance (max
+    # relative 5e-2), twice that in relative mode (the maximum carries error
+    # too); the pixels inside the band are counted.
+    import torch
+    L, S, B, BL = 2000, 640, 270, 100
+    cube = sensor_full
+    say("full sensor cube: oracle scores of every pixel (20 blocks, ridge 1e-6)")
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=BL, window_lines=L, rho=1e-6)
+    tau = float(np.quantile(ref, 1 - 5e-4))
+    st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                                      block_lines=BL, window_lines=L))
+    st.rx_push_lines(torch.from_numpy(cube).cuda())
+    st.rx_sync()
+    m_abs = st.mask_host(tau, rxm.RX_THR_ABS)
+    m_rel = st.mask_host(0.110, rxm.RX_THR_REL_MAX)
+    got = st.scores_host()
+    st.rx_destroy()
+    mx, p99 = err_summary(got, ref, B)
+    say(f"  bf16 full cube: max rel {mx:.3e}, p99 rel {p99:.3e}; tau_abs = {tau:.4f}, "
+        f"{int(m_abs.sum())} marked (oracle {int((ref > tau).sum())})")
+    assert_mask(m_abs, ref, tau, 5e-2, B, "bf16 abs at the (1 - 5e-4) quantile")
+    assert_mask(m_rel, ref, 0.110 * ref.max(), 2 * 5e-2, B, "bf16 relative 0.110")
 
 
 def test_stress_cube_full_size_sampled(rxm):

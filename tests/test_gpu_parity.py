@@ -106,6 +106,31 @@ def test_sensor_cube_blocks(rxm, prec, samples):
     assert_scores(got, ref, B, *TOL[prec], label=f"sensor {prec} S={samples}")
 
 
+@pytest.mark.parametrize("samples", [203, 640])
+@pytest.mark.parametrize("whiten", ["bf16", "fp16"])
+def test_fp16_covariance_product(rxm, samples, whiten):
+    # FP16 operands in the covariance product (FP32 accumulation) at 270
+    # bands with the 1e-6 ridge, against the oracle with the same ridge, at
+    # the BF16 row's tolerance (FP16 rounds 8x finer than BF16).  640-sample
+    # rows are whole 16-byte multiples and take the direct-to-LDS kernel;
+    # 203-sample rows are not and take the register-staged one.  Three
+    # blocks: several covariance splits per block and a short last block.
+    B, BL = 270, 16
+    lines = 40
+    cube = synth.sensor_cube(31, lines=lines, samples=samples, bands=B).cube
+    say(f"fp16 covariance: {lines}x{samples}x{B} u16, whitening {whiten}, blocks of {BL}, rho 1e-6")
+    ref, o = oracle_stream_scores(cube, B, samples, block_lines=BL, rho=1e-6)
+    st = run_stream(rxm, cube, "fp16", whiten, block_lines=BL, ridge_rel=1e-6)
+    got = st.scores_host()
+    assert_scores(got, ref, B, *TOL["bf16"], label=f"fp16 covariance + {whiten} whitening S={samples}")
+    n, mu, cov = st.rx_get_stats()
+    _, mu_r, cov_r = o.stats()
+    err = np.max(np.abs(cov - cov_r)) / np.abs(cov_r).max()
+    say(f"  fp16 covariance: max |cov err| / max|cov| = {err:.3e}")
+    assert np.max(np.abs(mu - mu_r)) <= 1e-12 * np.abs(mu_r).max()
+    assert err <= 2.5e-3      # the BF16 bound of the statistics test (2e-2) over 8: FP16 rounds 2^3 finer
+
+
 def test_sensor_cube_host_input_and_push_split(rxm):
     B, S = 120, 96
     cube = synth.sensor_cube(12, lines=60, samples=S, bands=B).cube

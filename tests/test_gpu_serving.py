@@ -213,3 +213,55 @@ def test_served_mix_with_causal_and_float_streams(rxm):
             assert_scores(got, ref, B, 1e-9, 1e-11, label=f"served B={B} S={S} causal={causal}")
         st.rx_destroy()
     srv.rx_server_destroy()
+
+
+def test_straddling_submit_is_refused_and_the_server_stays_consistent(rxm):
+    # A block that would cross its stream's window edge is refused at
+    # submission (nothing is queued, no stream changes); the streams already
+    # queued on the server, including the refused stream's earlier blocks,
+    # still produce exactly their scores alone.
+    B, S, W = 64, 128, 40
+    a_cube = synth.sensor_cube(61, lines=60, samples=S, bands=B).cube
+    b_cube = synth.sensor_cube(62, lines=48, samples=S, bands=B).cube
+    da, db = dev(a_cube), dev(b_cube)
+
+    def cfg(win):
+        return rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                               block_lines=32, window_lines=win)
+
+    alone_a = rxm.RxStream(cfg(W))
+    for l0, n in ((0, 24), (24, 16), (40, 20)):
+        alone_a.rx_push_lines(da[l0:l0 + n])
+    alone_a.rx_sync()
+    want_a = alone_a.scores_host()
+    alone_a.rx_destroy()
+    alone_b = rxm.RxStream(cfg(0))
+    for l0, n in ((0, 16), (16, 32)):
+        alone_b.rx_push_lines(db[l0:l0 + n])
+    alone_b.rx_sync()
+    want_b = alone_b.scores_host()
+    alone_b.rx_destroy()
+
+    srv = rxm.RxServer(1 << 30, 4)
+    sa = rxm.RxStream(cfg(W), server=srv)
+    sb = rxm.RxStream(cfg(0), server=srv)
+    srv.rx_server_submit(sa, da[0:24], 0)
+    srv.rx_server_submit(sb, db[0:16], 1)
+    with pytest.raises(rxm.RxError) as e:           # lines 24..48 would cross the edge at 40
+        srv.rx_server_submit(sa, da[24:48], 2)
+    assert e.value.status == rxm.RX_E_ARG
+    assert srv.rx_server_queued()[0] == 2
+    srv.rx_server_submit(sa, da[24:40], 3)          # up to the edge
+    srv.rx_server_submit(sa, da[40:60], 4)          # the next window
+    srv.rx_server_submit(sb, db[16:48], 5)
+    done = []
+    while len(done) < 5:
+        srv.rx_server_step()
+        done += srv.rx_server_poll(block=True)
+    assert sorted(done) == [0, 1, 3, 4, 5]
+    got_a, got_b = sa.scores_host(), sb.scores_host()
+    sa.rx_destroy()
+    sb.rx_destroy()
+    srv.rx_server_destroy()
+    assert np.array_equal(got_a.view(np.uint32), want_a.view(np.uint32))
+    assert np.array_equal(got_b.view(np.uint32), want_b.view(np.uint32))
