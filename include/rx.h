@@ -176,6 +176,27 @@ rx_status rx_scores_f64(rx_stream* s, double* out, int64_t max_px, int64_t* n_wr
 rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits,
                   int64_t max_bytes, int64_t* n_px, int32_t out_is_device, void* hip_stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: rx_mask
+ * with a device output that allocates nothing.  Same modes, tau, k, bit
+ * order and NaN rule as rx_mask; bits is a device pointer on the stream's
+ * device (any alignment, at least ceil(n/8) bytes = max_bytes), written after
+ * the work already queued on hip_stream and ordered before later work on it.
+ * Its working memory (maximum key, top-k state and histogram, the mask words
+ * before they are copied to bits) is one fixed device array of
+ * RX_MASK_NOALLOC_BYTES per GPU, located by rx_init on that GPU and held
+ * until the process ends; the pending set may hold at most
+ * RX_MASK_NOALLOC_MAX_PX pixels (RX_E_ARG beyond, nothing queued).  Every
+ * call on one GPU shares that array and it keeps the last call's contents:
+ * calls that overlap on one GPU (different rx_streams, or different host
+ * threads, whose work is not ordered on the device) race and must be
+ * serialised by the caller.  The stream itself (rx_init, rx_push_lines)
+ * still allocates as usual; only this call does not. */
+#define RX_MASK_NOALLOC_BYTES (4096 + (1 << 20))
+#define RX_MASK_NOALLOC_MAX_PX (1 << 23)
+rx_status rx_mask_noalloc(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits, int64_t max_bytes,
+                          int64_t* n_px, void* hip_stream);
+
 /* ---------------------------------------------------------------- ingest binning
  * Band selection and spectral binning of 16-bit counts (paper, Section
  * "System Implementation / Data Acquisition": out-of-range bands discarded,

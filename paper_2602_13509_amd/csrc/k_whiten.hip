@@ -660,7 +660,48 @@ __global__ void __launch_bounds__(NT) k_topk_ties(const void* sc, int f64, int64
   }
 }
 
+// Byte copy and word fill used by the allocation-free mask (kernels, so the
+// sequence can be captured into a HIP graph: no memset or memcpy nodes).
+__global__ void __launch_bounds__(NT) k_copy_bytes(const uint8_t* a, uint8_t* b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) b[i] = a[i];
+}
+__global__ void __launch_bounds__(NT) k_zero_words(uint32_t* w, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) w[i] = 0u;
+}
+
+// Working memory of the allocation-free mask entry point, one copy per GPU
+// (each device's code object holds its own), kept until the process ends:
+// the maximum key, the top-k state and histogram in the first 4 KiB, then
+// the mask words of up to 2^23 pixels.  Host code never passes this name to
+// a kernel: it takes the device address from rxk_noalloc_scratch.
+constexpr size_t kNoallocHead = 4096;
+constexpr size_t kNoallocBytes = kNoallocHead + (size_t(1) << 20);
+static __device__ __attribute__((aligned(256))) uint8_t scratch[kNoallocBytes];
+
 }  // namespace rxk
+
+// The current device's address of the allocation-free mask's working memory
+// and its size (the header part first, then the mask words).
+extern "C" hipError_t rxk_noalloc_scratch(void** ptr, size_t* head, size_t* bytes) {
+  *head = rxk::kNoallocHead;
+  *bytes = rxk::kNoallocBytes;
+  return hipGetSymbolAddress(ptr, HIP_SYMBOL(rxk::scratch));
+}
+
+extern "C" hipError_t rxk_launch_copy_bytes(const void* a, void* b, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + rxk::NT - 1) / rxk::NT;
+  hipLaunchKernelGGL(rxk::k_copy_bytes, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(rxk::NT), 0, st,
+                     static_cast<const uint8_t*>(a), static_cast<uint8_t*>(b), n);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t rxk_launch_zero_words(uint32_t* w, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + rxk::NT - 1) / rxk::NT;
+  hipLaunchKernelGGL(rxk::k_zero_words, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(rxk::NT), 0, st, w, n);
+  return hipGetLastError();
+}
 
 extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::LaunchSet* ls, int wg, int Bw,
                                         hipStream_t st) {

@@ -40,6 +40,10 @@ extern "C" hipError_t rxk_launch_bin(const uint16_t* in, uint16_t* out, int64_t 
 extern "C" hipError_t rxk_launch_tx_decode(const uint16_t* codes, int64_t n, const float* mslot, float tau,
                                            float* delta, uint32_t* bits, hipStream_t st);
 
+extern "C" hipError_t rxk_noalloc_scratch(void** ptr, size_t* head, size_t* bytes);
+extern "C" hipError_t rxk_launch_copy_bytes(const void* a, void* b, int64_t n, hipStream_t st);
+extern "C" hipError_t rxk_launch_zero_words(uint32_t* w, int64_t n, hipStream_t st);
+
 static_assert(sizeof(LaunchSet) < 4000, "kernel-argument descriptor set too large");
 
 // ---------------------------------------------------------------------------- errors
@@ -60,6 +64,33 @@ static rx_status fail(rx_status s, const char* fmt, ...) {
     hipError_t e_ = (call);                                                                 \
     if (e_ != hipSuccess) return fail(RX_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
+
+// ---------------------------------------------------------------------------- allocation-free mask
+// Device address of the allocation-free mask's working memory on each GPU
+// (a fixed device array in the whitening kernels' code object; each device
+// holds its own copy at its own address), looked up once per device by
+// rx_init with that device current.
+static constexpr int kMaxDevices = 64;
+static std::mutex g_na_mu;
+static void* g_na_ptr[kMaxDevices] = {};
+static size_t g_na_head = 0, g_na_bytes = 0;
+
+static rx_status noalloc_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RX_E_ARG, "device %d beyond the library's %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (g_na_ptr[dev]) return RX_OK;
+  void* p = nullptr;
+  size_t head = 0, bytes = 0;
+  const hipError_t e = rxk_noalloc_scratch(&p, &head, &bytes);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(RX_E_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+  }
+  g_na_ptr[dev] = p;
+  g_na_head = head;
+  g_na_bytes = bytes;
+  return RX_OK;
+}
 
 // ---------------------------------------------------------------------------- device buffers
 struct DevBuf {
@@ -445,6 +476,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
   if (cfg->device < 0 || cfg->device >= ndev) return fail(RX_E_ARG, "device %d not present (%d devices)", cfg->device, ndev);
   if (srv && srv->dev != cfg->device) return fail(RX_E_ARG, "stream device differs from the server's");
   HIPC(hipSetDevice(cfg->device));
+  if ((r = noalloc_setup(cfg->device)) != RX_OK) return r;
 
   rx_stream* s = new rx_stream();
   s->cfg = *cfg;
@@ -1149,6 +1181,48 @@ extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, 
     HIPC(hipStreamSynchronize(s->st));
     HIPC(hipMemcpy(bits, s->maskbits.p, (size_t)nbytes, hipMemcpyDeviceToHost));
   }
+  return RX_OK;
+}
+
+// rx_mask for callers that cannot allocate: the maximum key, top-k state and
+// histogram and the mask words live in the GPU's fixed working array (set
+// up by rx_init); the words are then copied to the caller's device bits by a
+// kernel.  No hipMalloc, hipFree, memset or library allocation on this path.
+extern "C" rx_status rx_mask_noalloc(rx_stream* s, double tau, int32_t mode, int64_t k, uint8_t* bits,
+                                     int64_t max_bytes, int64_t* n_px, void* hip_stream) {
+  rx_status r = check_stream(s);
+  if (r != RX_OK) return r;
+  if (!n_px) return fail(RX_E_ARG, "null n_px");
+  if (mode < RX_THR_ABS || mode > RX_THR_TOPK) return fail(RX_E_ARG, "bad threshold mode");
+  if (mode == RX_THR_TOPK && k < 0) return fail(RX_E_ARG, "k must be >= 0");
+  if (mode != RX_THR_TOPK && std::isnan(tau)) return fail(RX_E_ARG, "tau is NaN");
+  void* ws = nullptr;
+  size_t head = 0, cap = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    ws = g_na_ptr[s->dev];
+    head = g_na_head;
+    cap = g_na_bytes;
+  }
+  if (!ws) return fail(RX_E_STATE, "the allocation-free mask is not set up on device %d", s->dev);
+  const int64_t n = s->tail - s->head;
+  const int64_t nbytes = (n + 7) / 8, words = (n + 31) / 32;
+  *n_px = n;
+  if (n == 0) return RX_OK;
+  if (!bits || max_bytes < nbytes) return fail(RX_E_ARG, "mask buffer needs %lld bytes", (long long)nbytes);
+  const int64_t max_px = (int64_t)(cap - head) / 4 * 32;
+  if (n > max_px)
+    return fail(RX_E_ARG, "%lld pending pixels exceed the allocation-free mask's limit of %lld", (long long)n,
+                (long long)max_px);
+  HIPC(hipSetDevice(s->dev));
+  const void* src = static_cast<const char*>(s->pend[s->pcur].p) + (size_t)s->head * (s->sc_f64 ? 8 : 4);
+  uint32_t* wbits = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + head);
+  if ((r = after_caller(s, hip_stream)) != RX_OK) return r;
+  if (mode == RX_THR_TOPK && k == 0) HIPC(rxk_launch_zero_words(wbits, words, s->st));
+  else HIPC(rxk_launch_mask(src, s->sc_f64, n, mode, tau, k, wbits, ws, s->st));
+  HIPC(rxk_launch_copy_bytes(wbits, bits, nbytes, s->st));
+  HIPC(hipEventRecord(s->ev_done, s->st));
+  HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
   return RX_OK;
 }
 

@@ -22,6 +22,8 @@ RX_FP64, RX_FP32, RX_BF16, RX_FP16, RX_FP8_E4M3 = 0, 1, 2, 3, 4
 RX_THR_ABS, RX_THR_REL_MAX, RX_THR_TOPK = 0, 1, 2
 RX_FLAG_CAUSAL = 1
 RX_MAX_BANDS = 320
+RX_MASK_NOALLOC_BYTES = 4096 + (1 << 20)
+RX_MASK_NOALLOC_MAX_PX = 1 << 23
 
 STATUS_NAMES = {0: "RX_OK", -1: "RX_E_ARG", -2: "RX_E_NOMEM", -3: "RX_E_NOTREADY", -4: "RX_E_SINGULAR",
                 -5: "RX_E_DEVICE", -6: "RX_E_BUDGET", -7: "RX_E_STATE"}
@@ -34,6 +36,7 @@ EXPORTED = [
     "rx_get_whitener", "rx_server_create", "rx_server_destroy", "rx_stream_footprint", "rx_server_submit",
     "rx_server_step", "rx_server_poll", "rx_server_sync", "rx_server_queued", "rx_profile",
     "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode", "rx_bin_bands", "rx_split_plan",
+    "rx_mask_noalloc",
 ]
 
 
@@ -104,6 +107,7 @@ def _load():
         "rx_encode": (I32, [P, P, I64, C.POINTER(I64), P, P]),
         "rx_bin_bands": (I32, [P, I64, I32, I32, I32, I32, I32, I32, P, P]),
         "rx_split_plan": (I32, [C.POINTER(rx_config), I64, C.POINTER(I32), C.POINTER(I64)]),
+        "rx_mask_noalloc": (I32, [P, D, I32, I64, P, I64, C.POINTER(I64), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -204,6 +208,13 @@ class RxStream:
         size = out.numel() if hasattr(out, "numel") else out.size
         check(LIB.rx_mask(self.h, float(tau), mode, int(k), _ptr(out), size, C.byref(n), dev,
                           _stream_handle(stream) if dev else 0))
+        return n.value
+
+    def rx_mask_noalloc(self, tau: float, mode: int, k: int, out, stream=None) -> int:
+        """rx_mask_noalloc: device output (a uint8 tensor), no allocation."""
+        n = C.c_int64()
+        check(LIB.rx_mask_noalloc(self.h, float(tau), mode, int(k), _ptr(out), out.numel(), C.byref(n),
+                                  _stream_handle(stream)))
         return n.value
 
     def rx_encode(self, codes, max_out, stream=None) -> int:
