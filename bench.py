@@ -489,22 +489,22 @@ def headline_at_default_queues(steps):
 
 
 def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.0):
-    """budget: the server's HBM budget in bytes, or a float in (0, 1): that
-    fraction of the streams' total footprint (rx_stream_footprint), so that
-    only some streams fit at once.  compress > 1 replays the same arrivals
-    that many times faster (time-compressed replay)."""
     """Served form: 16 streams over every (S, B) in {320, 640, 1024} x {120,
     200, 270, 300} plus seeded repeats, Poisson block arrivals of 16-128 lines
     at 100-400 lines/s per stream, cumulative windows, BF16 path.  Each stream
     cycles blocks out of one resident 128-line sensor cube (the content does
-    not change the work).  Blocks are submitted at their arrival times (or all
-    at once) and the server is stepped continuously: whatever is queued joins
-    the next batched launch while earlier launches are still running.
-    Latency = arrival -> completion seen by a non-blocking poll.
-    With a budget too small for every stream, a stream that does not fit is
-    admitted (rx_init against the server) once finished streams have been
-    destroyed and their HBM released; its blocks wait meanwhile, and that
-    wait counts in their latency."""
+    not change the work).  The library's request loop (rx_server_start) runs
+    the server: blocks are submitted at their arrival times (or all at once)
+    and it batches whatever is queued into the next step while up to two
+    earlier steps are on the GPU.  Latency = submission -> completion, both
+    stamped on the library clock (the completion by the loop as soon as the
+    step's event has passed).
+    budget: the server's HBM budget in bytes, or a float in (0, 1): that
+    fraction of the streams' total footprint (rx_stream_footprint), so that
+    only some streams fit at once; a stream that does not fit is admitted
+    (rx_init against the server) once finished streams have been destroyed
+    and their HBM released, and its blocks wait meanwhile (counted in their
+    latency).  compress > 1 replays the same arrivals that many times faster."""
     from paper_2602_13509_amd import synth
     specs = synth.served_streams(0, n_streams=16, duration_s=seconds)
     streams, cubes, cfgs = [None] * len(specs), [], []
@@ -516,9 +516,12 @@ def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.
     if isinstance(budget, float):
         budget = int(budget * sum(rx.stream_footprint(c, 128) for c in cfgs))
     srv = rx.RxServer(budget, 16)
-    held = [[] for _ in specs]            # blocks of a stream not admitted yet: (tag, lines)
+    held = [[] for _ in specs]            # blocks of a stream not admitted yet: tags
     left = [len(sp.block_lines) for sp in specs]
     admitted_late = 0
+    ev = sorted((0.0 if replay_all_at_once else float(t) / compress, i, int(n))
+                for i, sp in enumerate(specs) for t, n in zip(sp.arrivals, sp.block_lines))
+    sub_ns, px_of, owner, lines_of = {}, {}, {}, {}
 
     def admit(late):
         nonlocal admitted_late
@@ -531,60 +534,61 @@ def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.
                         raise
                     continue
                 admitted_late += 1 if late else 0
-                for tg, n in held[i]:
-                    srv.rx_server_submit(streams[i], cubes[i][:n], tg)
+                for tg in held[i]:
+                    srv.rx_server_submit(streams[i], cubes[i][:lines_of[tg]], tg)
                 held[i].clear()
-    ev = sorted((0.0 if replay_all_at_once else float(t) / compress, i, int(n))
-                for i, sp in enumerate(specs) for t, n in zip(sp.arrivals, sp.block_lines))
-    arrive, px_of, owner = {}, {}, {}
     outs = [torch.empty(128 * sp.samples, dtype=torch.float32, device="cuda") for sp in specs]
     lat, total_px = [], 0
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     admit(False)
-    k, tag, launched = 0, 0, 0
+    srv.rx_server_start()
+    t0 = time.perf_counter()
+    k, tag, t_first, t_last = 0, 0, None, None
     while len(lat) < len(ev):
         now = time.perf_counter() - t0
         while k < len(ev) and ev[k][0] <= now:
-            t_arr, i, n = ev[k]
-            if streams[i] is not None:
+            _, i, n = ev[k]
+            sub_ns[tag] = rx.clock_ns()           # arrival stamp; a held block's wait counts too
+            t_first = sub_ns[tag] if t_first is None else t_first
+            px_of[tag], owner[tag], lines_of[tag] = n * specs[i].samples, i, n
+            if streams[i]:
                 srv.rx_server_submit(streams[i], cubes[i][:n], tag)
             else:
-                held[i].append((tag, n))
-            arrive[tag] = t_arr
-            px_of[tag] = n * specs[i].samples
-            owner[tag] = i
+                held[i].append(tag)
             tag += 1
             k += 1
-        launched += srv.rx_server_step()
+        tags, stamps = srv.rx_server_poll_ns(block=False)
         freed = False
-        for d in srv.rx_server_poll(block=False):
-            lat.append(time.perf_counter() - t0 - arrive[d])
+        for d, t_done in zip(tags, stamps):
+            lat.append((t_done - sub_ns[d]) * 1e-6)
+            t_last = t_done if t_last is None else max(t_last, t_done)
             total_px += px_of[d]
             i = owner[d]
             streams[i].rx_scores(outs[i])    # pop the block's scores (device to device)
             left[i] -= 1
             if left[i] == 0 and budget < (64 << 30):
-                streams[i].scores_host()     # a finished stream leaves: its HBM goes back to the server
-                streams[i].rx_destroy()
+                streams[i].rx_destroy()      # a finished stream leaves: its HBM goes back to the server
                 streams[i] = False
                 freed = True
         if freed:
             admit(True)
-        if now > seconds + 120.0:
+        if not tags:
+            time.sleep(0.0002 if k < len(ev) else 0.0001)
+        if now > seconds / compress + 120.0:
             raise RuntimeError(f"served run did not drain: {len(lat)} of {len(ev)} blocks done")
-    t_end = time.perf_counter() - t0
+    srv.rx_server_stop()
+    wall = (t_last - t_first) * 1e-9
     for st in streams:
         if st:
             st.scores_host()                      # drain the FIFOs (not timed)
             st.rx_destroy()
     srv.rx_server_destroy()
-    lat = np.array(lat) * 1e3
+    lat = np.array(lat)
     offered = sum(int(np.sum(sp.block_lines)) * sp.samples for sp in specs) / (seconds / compress)
     return {"streams": len(specs), "blocks": len(ev), "arrival_window_s": seconds,
             "all_at_once": replay_all_at_once, "time_compression": compress, "hbm_budget_bytes": int(budget),
-            "streams_admitted_late": admitted_late, "px": int(total_px), "wall_s": t_end,
-            "px_per_s": total_px / t_end, "offered_px_per_s": offered,
+            "streams_admitted_late": admitted_late, "px": int(total_px), "wall_s": wall,
+            "px_per_s": total_px / wall, "offered_px_per_s": offered, "request_loop": True,
             "latency_ms": {"p50": float(np.median(lat)), "p99": float(np.quantile(lat, 0.99)),
                            "max": float(lat.max())}}
 
@@ -639,6 +643,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="arrival window of the served-streams run (0 skips it)")
     ap.add_argument("--skip-fp64", action="store_true", help="skip the plain FP64 path (short profiling runs)")
+    ap.add_argument("--profile", action="store_true",
+                    help="profiler runs: the mixed-path steps, the one-block pushes and the block latency "
+                         "only (then the reference copy, if asked); prints no JSON line")
     ap.add_argument("--headline-only", action="store_true",
                     help="time the mixed-path step only and print its JSON line (used for the 4-queue figure)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -664,6 +671,18 @@ def main():
                                                      repeats=0 if args.headline_only else 10)
     if args.headline_only:
         print(json.dumps({"value": npx / t_mix, "ms_per_step": t_mix * 1e3, "steps": args.steps}), flush=True)
+        return
+    if args.profile:
+        obp = one_block_pushes(rx, torch, x, "bf16", steps=3, warmup=1)
+        p50, p99 = latency(rx, torch, x, "bf16", 20)
+        log(f"profile run: one-block pushes {obp['px_per_s']:.4e} px/s; block latency p50 {p50:.3f} ms")
+        if args.copy_mib > 0:
+            src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"reference copy: {args.copy_mib} MiB device to device")
         return
     log(f"mixed path over 10 repeated {args.steps}-step regions: median {spread['median_px_per_s']:.4e} px/s "
         f"(min {spread['min_px_per_s']:.4e}, max {spread['max_px_per_s']:.4e})")
@@ -771,6 +790,20 @@ def main():
                 phases[p]["mfma_frac"] = r["mfma_frac"]
                 phases[p]["frac_measured"] = r["achieved"] / hbm_meas
 
+    # the plain FP64 path's two products against the FP64 matrix-core peak
+    # (its dominant kernels; phase times from its own profiled pass)
+    fp64_roof = None
+    if not args.skip_fp64:
+        fp64_roof = {}
+        for i, p in enumerate(PHASES):
+            if p in ("covariance", "whiten_score") and n_64[i]:
+                sec = ms_64[i] / n_64[i] * 1e-3
+                fl = work[p][1]
+                fp64_roof[p] = {"bound": "mfma", "achieved": fl / sec / 1e12, "peak": PEAK_TFLOPS["fp64"],
+                                "unit": "TFLOP/s", "frac": fl / sec / 1e12 / PEAK_TFLOPS["fp64"],
+                                "avg_launch_ms": ms_64[i] / n_64[i]}
+        log("fp64 path: " + ", ".join(f"{k} {v['frac']:.3f} of FP64 peak" for k, v in fp64_roof.items()))
+
     value = npx / t_mix
     rec = {
         "metric": "pixel-spectra/s scored at 270 bands (mixed vs FP64 path); p99 line latency",
@@ -780,7 +813,8 @@ def main():
         "config": {"workload": "sensor cube 2000 lines x 640 samples x 270 bands uint16, 20 blocks of 100 "
                                "lines, update-then-score, BF16 covariance + whitening, FP64 factor, ridge 1e-6",
                    "lines": LINES, "samples": SAMPLES, "bands": BANDS, "block_lines": BLOCK},
-        "fp64_path": None if args.skip_fp64 else {"value": npx / t_64, "ms_per_step": t_64 * 1e3, "steps": k64},
+        "fp64_path": None if args.skip_fp64 else {"value": npx / t_64, "ms_per_step": t_64 * 1e3, "steps": k64,
+                                                  "roofline": fp64_roof},
         "mixed_over_fp64": None if args.skip_fp64 else t_64 / t_mix,
         "fp32_path": None if args.skip_fp64 else {"value": npx / t_32, "ms_per_step": t_32 * 1e3, "steps": k64},
         "value_repeats": spread,

@@ -62,7 +62,13 @@ typedef enum {
 } rx_status;
 
 typedef enum { RX_IN_U16 = 0, RX_IN_F32 = 1, RX_IN_F64 = 2 } rx_in_type;
-typedef enum { RX_BIL = 0 /* band-interleaved by line: [line][band][sample] */ } rx_layout;
+/* Layout of pushed lines.  RX_BIL: band-interleaved by line [line][band][sample], what the
+ * push-broom imager delivers (paper, Section "System Implementation / Data Acquisition") and
+ * what the kernels read.  RX_BIP: band-interleaved by pixel [line][sample][band]; each push is
+ * first transposed into a library-owned BIL copy (one extra read and write of the lines on the
+ * device; the scores are bit for bit those of the same lines pushed as BIL).  Served streams
+ * take BIL blocks only. */
+typedef enum { RX_BIL = 0, RX_BIP = 1 } rx_layout;
 typedef enum { RX_FP64 = 0, RX_FP32 = 1, RX_BF16 = 2, RX_FP16 = 3, RX_FP8_E4M3 = 4 } rx_prec;
 typedef enum { RX_THR_ABS = 0, RX_THR_REL_MAX = 1, RX_THR_TOPK = 2 } rx_thr_mode;
 
@@ -74,8 +80,13 @@ typedef struct rx_config {
   int32_t samples;        /* S >= 1 samples (pixels) per line */
   int32_t in_type;        /* rx_in_type of the pushed values */
   int32_t bit_depth;      /* u16 input: values must be < 2^bit_depth (informational), 0 = 16 */
-  int32_t layout;         /* rx_layout; only RX_BIL */
-  int32_t syrk_prec;      /* covariance-product precision: FP64, FP32, BF16 or FP16 */
+  int32_t layout;         /* rx_layout: RX_BIL or RX_BIP (not for served streams) */
+  int32_t syrk_prec;      /* covariance-product precision: FP64, FP32, BF16, FP16 or FP8_E4M3.
+                             FP8: each block's centred values are scaled per band by 2^-e
+                             (e from the block's first line: its largest deviation from the
+                             shift lands at or below 224, half the format's range), rounded
+                             to E4M3, multiplied with FP32 accumulation and scaled back
+                             exactly; larger values saturate at 448 and are counted */
   int32_t whiten_prec;    /* whitening precision: FP64, FP32, BF16, FP16 or FP8_E4M3 */
   int32_t ddof;           /* covariance normaliser 1/(N - ddof); 0 (default) or 1 */
   int32_t block_lines;    /* 0: each push is one block; >0: pushes are cut into blocks of at
@@ -111,6 +122,8 @@ typedef struct rx_counters {
                                statistics, scored NaN, never marked) */
   int64_t fp8_saturated;    /* FP8 E4M3 whitening: centred, band-scaled input values beyond the
                                format's range (|v| > 464), stored as +-448 */
+  int64_t fp8_syrk_saturated; /* FP8 E4M3 covariance product: centred, band-scaled values beyond
+                               the format's range (|v| > 464), stored as +-448 */
 } rx_counters;
 
 /* Fill *cfg with defaults for B bands and S samples: u16 input, 12-bit,
@@ -130,7 +143,8 @@ rx_status rx_config_init(rx_config* cfg, int32_t bands, int32_t samples);
  * device refuses. */
 rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
 
-/* Push n_lines >= 1 lines, BIL [n_lines][B][S] of cfg->in_type, contiguous.
+/* Push n_lines >= 1 lines, BIL [n_lines][B][S] (or BIP [n_lines][S][B] with
+ * cfg->layout = RX_BIP) of cfg->in_type, contiguous.
  * is_device_ptr = 0: lines is host memory, copied before the call returns
  * (the caller may reuse it at once).  is_device_ptr = 1: lines is device
  * memory on cfg->device; it is read asynchronously and must stay unchanged
@@ -328,7 +342,10 @@ rx_status rx_server_submit(rx_server* srv, rx_stream* s, const void* lines_dev, 
 
 /* Launch the oldest queued block of every stream that has one, all in one
  * batched pass (statistics, factorisations and whitening of every stream
- * in shared launches).  Asynchronous; *n_blocks = blocks launched. */
+ * in shared launches).  Asynchronous; *n_blocks = blocks launched.  The
+ * server runs a step over three HIP queues (statistics; factorisation;
+ * whitening), so one step's statistics overlap the previous step's
+ * factorisation and whitening. */
 rx_status rx_server_step(rx_server* srv, int32_t* n_blocks);
 
 /* Report finished blocks in launch order: up to max_tags tags are written.
@@ -337,6 +354,34 @@ rx_status rx_server_poll(rx_server* srv, uint64_t* tags, int32_t max_tags, int32
 
 /* Wait for every launched block. */
 rx_status rx_server_sync(rx_server* srv);
+
+/* Persistent request loop (the paper's stages run continuously on their own
+ * cores, Section "System Implementation / Flight System"; here one library
+ * thread per server).  rx_server_start starts a thread that, until
+ * rx_server_stop, launches a batched step whenever blocks are queued and
+ * fewer than two steps are in flight (blocks arriving meanwhile join the
+ * next step: continuous batching), and stamps every finished block with
+ * rx_clock_ns() as soon as its step's completion event is seen (within tens
+ * of microseconds).  While it runs, rx_server_step returns RX_E_STATE and
+ * rx_server_poll / rx_server_poll_ns return the blocks it has collected
+ * (block = 1: after every queued and launched block has finished).  Calls
+ * on the server's streams (rx_scores, rx_mask, ...) take the server's lock
+ * and may be made from other threads.  rx_server_stop joins the thread and
+ * returns the first error the loop met (launched blocks keep running; poll
+ * or rx_server_sync to wait for them).  RX_E_STATE when already running /
+ * not live. */
+rx_status rx_server_start(rx_server* srv);
+rx_status rx_server_stop(rx_server* srv);
+
+/* As rx_server_poll, also writing each block's completion stamp (ns of
+ * rx_clock_ns, taken by the request loop; 0 for blocks collected by a
+ * direct poll without the loop) to done_ns[] when it is not NULL. */
+rx_status rx_server_poll_ns(rx_server* srv, uint64_t* tags, int64_t* done_ns, int32_t max_tags, int32_t* n_done,
+                            int32_t block);
+
+/* The library's monotonic clock in nanoseconds (steady clock), for stamping
+ * block arrivals on the same time base as rx_server_poll_ns. */
+int64_t rx_clock_ns(void);
 
 /* Queue depth, blocks in flight and admitted bytes (any pointer may be NULL). */
 rx_status rx_server_queued(rx_server* srv, int32_t* queued, int32_t* inflight, size_t* used_bytes);

@@ -89,6 +89,36 @@ __global__ void __launch_bounds__(NT) k_shift(LaunchSet ls) {
     if (P != P_F64) c = (double)(float)c;
   }
   if (lane == 0) d.shift[(int64_t)b * d.Bp + band] = c;
+  if constexpr (P == P_FP8) {
+    // FP8 operand band scale 2^-e: the first line's largest deviation from
+    // the shift lands at or below 224, half of E4M3's largest value (448),
+    // leaving a factor of two for the rest of the block; values beyond 448
+    // saturate and are counted
+    float sc = 0.0f;
+    if (band < d.B) {
+      const T* row = static_cast<const T*>(d.x) + ((int64_t)b * d.blk_lines * d.B + band) * d.S;
+      const float cf = (float)c;
+      float m = 0.0f;
+      for (int i = lane; i < d.S; i += 64) {
+        bool ok = true;
+        if constexpr (IN != IN_U16) ok = d.valid[(int64_t)b * d.blk_lines * d.S + i] != 0;
+        const float v = ok ? __builtin_fabsf((float)row[i] - cf) : 0.0f;
+        m = v > m ? v : m;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const float t = __shfl_xor(m, o, 64);
+        m = t > m ? t : m;
+      }
+      int e = 0;
+      if (m > 0.0f) {
+        int ex;
+        (void)frexpf(m / 224.0f, &ex);           // m / 224 in [2^(ex-1), 2^ex)
+        e = ex;                                  // m 2^-e <= 224
+      }
+      sc = ldexpf(1.0f, -e);
+    }
+    if (lane == 0 && band < d.Bp) d.sscale[(int64_t)b * d.Bp + band] = sc;
+  }
 }
 
 // ---------------------------------------------------------------------------- covariance product
@@ -261,12 +291,14 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
   // Raw sums are exact: uint32 for 16-bit input (at most 80 chunks x 8 values
   // x 65535 per thread), FP64 otherwise.
   using RS = typename std::conditional<IN == IN_U16, uint32_t, double>::type;
-  float shf[S2IT];
+  float shf[S2IT], bsc[S2IT];               // shift, and the FP8 operand's band scale
   RS rawsum[S2IT];
+  uint32_t nclip = 0;                         // FP8: operand values beyond the format's range
 #pragma unroll
   for (int q = 0; q < S2IT; ++q) {
     const int r = (tid + S2NT * q) >> 3;
     shf[q] = (r < d.B) ? (float)d.shift[(int64_t)b * d.Bp + r] : 0.0f;
+    bsc[q] = (P == P_FP8 && r < d.B) ? d.sscale[(int64_t)b * d.Bp + r] : 1.0f;
     rawsum[q] = RS(0);
   }
   auto row_of = [&](int q) { const int it = tid + S2NT * q; return (it < d.Bp * 8) ? (it >> 3) : -1; };
@@ -319,13 +351,24 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
         float dv;
         if constexpr (IN == IN_F64) dv = (float)(vv[j] - (double)d.shift[(int64_t)b * d.Bp + r]);
         else dv = (float)vv[j] - shf[q];
+        if constexpr (P == P_FP8) {
+          dv *= bsc[q];                       // a power of two: exact
+          nclip += ok ? e4m3_clips(dv) : 0u;
+        }
         o[j] = to_storage<P>(ok ? dv : 0.0f);
         if (ok) rawsum[q] += (RS)vv[j];
       }
-      uint4 ow;
-      ow.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16); ow.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-      ow.z = (uint32_t)o[4] | ((uint32_t)o[5] << 16); ow.w = (uint32_t)o[6] | ((uint32_t)o[7] << 16);
-      *reinterpret_cast<uint4*>(&tile[buf][r * S2LDK + k0]) = ow;
+      if constexpr (sizeof(S) == 1) {
+        uint2 ow;
+        ow.x = (uint32_t)o[0] | ((uint32_t)o[1] << 8) | ((uint32_t)o[2] << 16) | ((uint32_t)o[3] << 24);
+        ow.y = (uint32_t)o[4] | ((uint32_t)o[5] << 8) | ((uint32_t)o[6] << 16) | ((uint32_t)o[7] << 24);
+        *reinterpret_cast<uint2*>(&tile[buf][r * S2LDK + k0]) = ow;
+      } else {
+        uint4 ow;
+        ow.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16); ow.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+        ow.z = (uint32_t)o[4] | ((uint32_t)o[5] << 16); ow.w = (uint32_t)o[6] | ((uint32_t)o[7] << 16);
+        *reinterpret_cast<uint4*>(&tile[buf][r * S2LDK + k0]) = ow;
+      }
     }
   };
 
@@ -384,9 +427,16 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int gi = 16 * (rr0 + i) + M::out_row(lane >> 4, e), gj = 16 * (rc0 + j) + lr;
-          out[(int64_t)gi * d.Bp + gj] = acc[i][j][e];
+          float v = acc[i][j][e];
+          if constexpr (P == P_FP8) {
+            // undo the band scales (powers of two): the partial of the unscaled products
+            const float si = d.sscale[(int64_t)b * d.Bp + gi], sj = d.sscale[(int64_t)b * d.Bp + gj];
+            v = (si > 0.0f && sj > 0.0f) ? (v / si) / sj : 0.0f;
+          }
+          out[(int64_t)gi * d.Bp + gj] = v;
         }
       }
+  if constexpr (P == P_FP8) wave_count(d.cnt64 + 2, nclip);
   // raw band sums: the 8 segments of a row are 8 adjacent lanes
 #pragma unroll
   for (int q = 0; q < S2IT; ++q) {
@@ -803,6 +853,18 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const r
     return hipGetLastError();
   }
   if (wg <= 0) return hipSuccess;
+  if (prec == P_FP8) {                       // FP8 operands with band scales: the register-staged kernels
+    if (phase == 0) {
+      if (in_type == IN_U16) hipLaunchKernelGGL((k_shift<IN_U16, P_FP8>), dim3(wg), dim3(NT), 0, st, *ls);
+      else if (in_type == IN_F32) hipLaunchKernelGGL((k_shift<IN_F32, P_FP8>), dim3(wg), dim3(NT), 0, st, *ls);
+      else hipLaunchKernelGGL((k_shift<IN_F64, P_FP8>), dim3(wg), dim3(NT), 0, st, *ls);
+    } else {
+      if (in_type == IN_U16) hipLaunchKernelGGL((k_syrk2<IN_U16, P_FP8>), dim3(wg), dim3(S2NT), 0, st, *ls);
+      else if (in_type == IN_F32) hipLaunchKernelGGL((k_syrk2<IN_F32, P_FP8>), dim3(wg), dim3(S2NT), 0, st, *ls);
+      else hipLaunchKernelGGL((k_syrk2<IN_F64, P_FP8>), dim3(wg), dim3(S2NT), 0, st, *ls);
+    }
+    return hipGetLastError();
+  }
   if (phase == 1 && in_type == IN_U16 && (prec == P_BF16 || prec == P_F16)) {
     // aligned 16-bit batches take the direct-load kernel, the others the
     // register-staged one; the choice is per batch, so a block's partials

@@ -268,6 +268,7 @@ struct BatchDesc {
   int* nbadl;             // [lines of the batch] pixels with a non-finite band
   // statistics scratch
   double* shift;          // [nblk][Bp] per-block centring shift (FP32-representable on mixed paths)
+  float* sscale;          // [nblk][Bp] FP8 covariance operand: band scale 2^-e (0 past the band count)
   void* part;             // [nblk][ks][Bp*Bp] centred scatter partials, lower part (float, or double on FP64)
   double* psum;           // [nblk][ks][Bp] raw per-band sums of each split (written by diagonal super-tiles)
   double* mu_snap;        // [nblk][Bp] window mean after block b
@@ -284,13 +285,18 @@ struct BatchDesc {
   // factorisation
   double* w64;            // [nblk][Bp*Bp] W = L^{-1} S (row-major lower, FP64)
   void* wlp;              // [nblk][Bp*Bp] whitening operand in whiten precision, scaled
+  double* lfac;           // [nblk][lf_stride] factor hand-off between the factor kernels: the
+                          // diagonal inverses Y_k and the off-diagonal L_ik tiles in matrix-core
+                          // operand order, then the equilibration scale [Bp]
+  int64_t lf_stride;      // doubles per block of lfac
   float* iscale;          // [nblk][Bp] input scale 2^-e_k applied to centred values
   float* oscale;          // [nblk][Bp] output row scale 2^f_i
   int* status;            // [nblk] 0 ok, 1 singular, 2 not ready
   int* clipflag;          // [nblk] FP8 whitening of 16-bit input: 1 if a value of block b was clipped
   unsigned int* nsing;    // stream counters: [0] singular blocks, [1] blocks scored while not ready
   unsigned long long* cnt64;   // stream counters: [0] pixels with a non-finite band,
-                               // [1] FP8 operand values that saturated
+                               // [1] FP8 whitening operand values that saturated,
+                               // [2] FP8 covariance operand values that saturated
   void* scores;           // scores of the batch's pixels (float, or double on FP64 whitening)
 };
 

@@ -10,7 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -18,6 +20,7 @@
 #include <deque>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/rx.h"
@@ -37,6 +40,8 @@ extern "C" hipError_t rxk_launch_tx_encode(const void* sc, int f64, int64_t n, u
                                            hipStream_t st);
 extern "C" hipError_t rxk_launch_bin(const uint16_t* in, uint16_t* out, int64_t lines, int bands, int samples, int b0,
                                      int nbo, int k, hipStream_t st);
+extern "C" hipError_t rxk_launch_bip_to_bil(const void* in, void* out, int64_t lines, int bands, int samples, int esz,
+                                            hipStream_t st);
 extern "C" hipError_t rxk_launch_tx_decode(const uint16_t* codes, int64_t n, const float* mslot, float tau,
                                            float* delta, uint32_t* bits, hipStream_t st);
 
@@ -145,7 +150,7 @@ static int pad32(int b) { return 32 * ceil_div(b, 32); }
 static size_t in_elem_size(int t) { return t == RX_IN_U16 ? 2 : (t == RX_IN_F32 ? 4 : 8); }
 // Splits depend only on the block (never on the batch), so a block's result
 // is the same alone and in any batch.
-static bool whole_triangle(int sp) { return sp == RX_BF16 || sp == RX_FP16; }
+static bool whole_triangle(int sp) { return sp == RX_BF16 || sp == RX_FP16 || sp == RX_FP8_E4M3; }
 // The covariance kernels keep each split's raw band sums of 16-bit input as
 // exact uint32 per thread, and a thread adds 8 values of at most 65535 per
 // chunk: a split of at most kMaxChunksPerSplit chunks cannot wrap
@@ -199,8 +204,15 @@ struct Block {
 };
 
 struct Sizes {
-  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status, ev, coef, valid, nbadl;
+  size_t shift, part, psum, mu, m2, nsnap, w64, wlp, scl, status, ev, coef, valid, nbadl, lfac, sscale;
 };
+
+// Doubles per block of the factor hand-off: T diagonal inverses and
+// T (T - 1) / 2 off-diagonal tiles of 256 doubles, then the Bp scales.
+static int64_t lf_stride_for(int Bp) {
+  const int64_t T = Bp / 16;
+  return 256 * (T + T * (T - 1) / 2) + Bp;
+}
 
 static Sizes scratch_sizes(int B, int S, int in_type, int sp, int nblk, int blk_lines) {
   const int Bp = pad16(B), Bw = pad32(Bp);
@@ -221,6 +233,8 @@ static Sizes scratch_sizes(int B, int S, int in_type, int sp, int nblk, int blk_
   z.status = (size_t)nblk * 8;             // status, then the FP8 clip flags
   z.ev = (size_t)nblk * Bp * 8;
   z.coef = (size_t)nblk * 8;
+  z.lfac = (size_t)nblk * lf_stride_for(Bp) * 8;
+  z.sscale = sp == RX_FP8_E4M3 ? (size_t)nblk * Bp * 4 : 0;
   // float input: per-pixel validity (by parity, read by the whitening) and
   // per-line counts of pixels with a non-finite band
   const bool fl = in_type != RX_IN_U16;
@@ -265,17 +279,22 @@ struct rx_stream {
                                           // when float input holds non-finite pixels)
   int64_t lines_seen = 0;
   // batch scratch
-  DevBuf nsing, evb, dvb, coefb, nbvb, nbadl, shift, part, psum;
+  DevBuf nsing, evb, dvb, coefb, nbvb, nbadl, shift, part, psum, sscale;
   // by parity: a batch's M2 and count snapshots are read by its factor, and
   // its mean snapshot, W, scales and status by its whitening, while the next
   // batch's product and merge run on queue A
-  DevBuf m2s[2], nsnap[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2], valid[2];
+  DevBuf m2s[2], nsnap[2], mu[2], w64[2], wlp[2], isc[2], osc[2], status[2], valid[2], lfac[2];
   unsigned last_nsing = 0;
   // pending scores
   DevBuf pend[2];
   int pcur = 0;
   int64_t head = 0, tail = 0;
   int sc_f64 = 0;
+  // band-interleaved-by-pixel input: each push is first transposed into
+  // this BIL copy (on queue A), which the path then reads; ev_bip marks the
+  // end of the last push that read it
+  DevBuf bip;
+  hipEvent_t ev_bip = nullptr;
   // host input staging
   DevBuf stage;
   void* host_pin = nullptr;
@@ -299,6 +318,17 @@ struct rx_stream {
   int64_t q_lines = 0;                    // served: lines submitted and not yet launched
 };
 
+struct rx_server;
+static std::mutex* server_mutex(rx_stream* s);
+// Calls on a served stream take the server's lock: its request loop may be
+// launching the stream's blocks (and moving its score FIFO) meanwhile.
+struct SrvLock {
+  std::unique_lock<std::mutex> lk;
+  explicit SrvLock(rx_stream* s) {
+    if (std::mutex* m = server_mutex(s)) lk = std::unique_lock<std::mutex>(*m);
+  }
+};
+
 static rx_status check_stream(rx_stream* s) {
   if (!s) return fail(RX_E_ARG, "null stream");
   if (s->magic != kMagic) return fail(RX_E_STATE, "stream handle is not live");
@@ -317,17 +347,39 @@ struct InFlight {
   hipEvent_t ev;
   std::vector<std::pair<rx_stream*, uint64_t>> items;
 };
+struct Done {
+  uint64_t tag;
+  int64_t t_ns;          // completion seen by the request loop (rx_clock_ns); 0 when polled directly
+};
+static int64_t clock_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
 struct rx_server {
   uint32_t magic = 0x52585356u;   // "RXSV"
   size_t budget = 0, used = 0;
   int max_streams = 0, n_streams = 0;
   int dev = 0;
-  hipStream_t st = nullptr;
+  // three queues as for an unserved stream: A (shift, covariance, merge),
+  // B (factorisation), st = C (whitening, score pops); consecutive steps
+  // overlap, ordered by the events below (step parity spar)
+  hipStream_t st = nullptr, stA = nullptr, stB = nullptr;
+  hipEvent_t ev_merged[2] = {nullptr, nullptr}, ev_fact = nullptr, ev_white[2] = {nullptr, nullptr};
+  int spar = 0;
   std::deque<Pending> queue;
   std::deque<InFlight> inflight;
+  std::deque<Done> done;                  // finished blocks collected by the request loop
   std::vector<hipEvent_t> free_events;
   std::mutex mu;
+  // persistent request loop (rx_server_start / rx_server_stop)
+  std::thread loop;
+  std::condition_variable cv;
+  bool running = false, stop = false;
+  rx_status loop_err = RX_OK;
+  std::string loop_msg;
+  int64_t loop_steps = 0;
 };
+static std::mutex* server_mutex(rx_stream* s) { return (s && s->srv) ? &s->srv->mu : nullptr; }
 
 // ---------------------------------------------------------------------------- config
 extern "C" rx_status rx_config_init(rx_config* cfg, int32_t bands, int32_t samples) {
@@ -350,8 +402,8 @@ static rx_status validate(const rx_config* c) {
   if (c->bands < 1 || c->bands > RX_MAX_BANDS) return fail(RX_E_ARG, "bands must be in [1, %d]", RX_MAX_BANDS);
   if (c->samples < 1) return fail(RX_E_ARG, "samples must be >= 1");
   if (c->in_type < RX_IN_U16 || c->in_type > RX_IN_F64) return fail(RX_E_ARG, "bad in_type");
-  if (c->layout != RX_BIL) return fail(RX_E_ARG, "only the BIL layout is supported");
-  if (c->syrk_prec < RX_FP64 || c->syrk_prec > RX_FP16) return fail(RX_E_ARG, "syrk_prec must be FP64, FP32, BF16 or FP16");
+  if (c->layout != RX_BIL && c->layout != RX_BIP) return fail(RX_E_ARG, "layout must be RX_BIL or RX_BIP");
+  if (c->syrk_prec < RX_FP64 || c->syrk_prec > RX_FP8_E4M3) return fail(RX_E_ARG, "bad syrk_prec");
   if (c->whiten_prec < RX_FP64 || c->whiten_prec > RX_FP8_E4M3) return fail(RX_E_ARG, "bad whiten_prec");
   if (c->ddof != 0 && c->ddof != 1) return fail(RX_E_ARG, "ddof must be 0 or 1");
   if (c->block_lines < 0 || c->window_lines < 0) return fail(RX_E_ARG, "block_lines and window_lines must be >= 0");
@@ -366,8 +418,10 @@ static size_t stream_bytes(const rx_config* c, int max_block_lines) {
   const int slots = 1 + ((c->flags & RX_FLAG_CAUSAL) ? 1 : 0);     // causal: the window before the block
   const Sizes z = scratch_sizes(c->bands, c->samples, c->in_type, c->syrk_prec, slots, std::max(1, max_block_lines));
   const size_t state = 2 * ((size_t)(Bp + 1) * 8 + (size_t)Bp * Bp * 8);
-  const size_t scr = z.shift + z.part + z.psum + z.mu + z.m2 + z.nsnap + z.w64 + z.wlp + 2 * z.scl + z.status +
-                     2 * z.ev + 2 * z.coef + 2 * z.valid + z.nbadl;
+  // the snapshot, factor and validity buffers come in two parity sets
+  // (served streams too: consecutive server steps overlap)
+  const size_t par = z.mu + z.m2 + z.nsnap + z.w64 + z.wlp + 2 * z.scl + z.status + z.valid + z.lfac;
+  const size_t scr = z.shift + z.part + z.psum + 2 * par + 2 * z.ev + 2 * z.coef + z.nbadl + z.sscale;
   const size_t esz = c->whiten_prec == RX_FP64 ? 8 : 4;
   const size_t pend = 2 * (size_t)std::max(1, max_block_lines) * c->samples * esz;
   return state + scr + pend;
@@ -408,7 +462,7 @@ static void free_stream(rx_stream* s) {
                     &s->nsnap[1], &s->mu[0],
                     &s->mu[1], &s->m2s[0], &s->nsnap[0], &s->w64[0], &s->w64[1], &s->wlp[0], &s->wlp[1], &s->isc[0],
                     &s->isc[1], &s->osc[0], &s->osc[1], &s->status[0], &s->status[1], &s->evb, &s->dvb, &s->coefb,
-                    &s->nbvb, &s->valid[0], &s->valid[1], &s->nbadl, &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
+                    &s->nbvb, &s->valid[0], &s->valid[1], &s->lfac[0], &s->lfac[1], &s->nbadl, &s->bip, &s->sscale, &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
   for (DevBuf* b : bufs) dev_free(*b);
   if (s->host_pin) (void)hipHostFree(s->host_pin);
   s->host_pin = nullptr;
@@ -417,7 +471,7 @@ static void free_stream(rx_stream* s) {
   s->prof_pool.clear();
   s->prof_open.clear();
   hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_merged[0], s->ev_merged[1],
-                      s->ev_fact, s->ev_white[0], s->ev_white[1], s->ev_last};
+                      s->ev_fact, s->ev_white[0], s->ev_white[1], s->ev_last, s->ev_bip};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
   if (s->own_st) {
@@ -434,6 +488,7 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
   if ((r = dev_ensure(s->shift, z.shift, s)) != RX_OK) return r;
   if ((r = dev_ensure(s->part, z.part, s)) != RX_OK) return r;
   if ((r = dev_ensure(s->psum, z.psum, s)) != RX_OK) return r;
+  if (z.sscale && (r = dev_ensure(s->sscale, z.sscale, s)) != RX_OK) return r;
   bool zeroed = false;
   for (int q = 0; q < s->npar; ++q) {
     if ((r = dev_ensure(s->m2s[q], z.m2, s)) != RX_OK) return r;
@@ -451,6 +506,7 @@ static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
     if ((r = dev_ensure(s->osc[q], z.scl, s)) != RX_OK) return r;
     if ((r = dev_ensure(s->status[q], z.status, s)) != RX_OK) return r;
     if (z.valid && (r = dev_ensure(s->valid[q], z.valid, s)) != RX_OK) return r;
+    if ((r = dev_ensure(s->lfac[q], z.lfac, s)) != RX_OK) return r;
   }
   // buffers zeroed on queue C must be clear before queue B's factor writes
   // them (only after a growth: otherwise B must not wait behind C)
@@ -475,6 +531,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
   HIPC(hipGetDeviceCount(&ndev));
   if (cfg->device < 0 || cfg->device >= ndev) return fail(RX_E_ARG, "device %d not present (%d devices)", cfg->device, ndev);
   if (srv && srv->dev != cfg->device) return fail(RX_E_ARG, "stream device differs from the server's");
+  if (srv && cfg->layout != RX_BIL) return fail(RX_E_ARG, "served streams take BIL blocks");
   HIPC(hipSetDevice(cfg->device));
   if ((r = noalloc_setup(cfg->device)) != RX_OK) return r;
 
@@ -514,8 +571,9 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
     s->srv = srv;
     s->footprint = need;
     s->st = srv->st;
-    s->stA = s->stB = s->st;
-    s->npar = 1;
+    s->stA = srv->stA;
+    s->stB = srv->stB;
+    s->npar = 2;
   } else {
     s->own_st = true;
     if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
@@ -525,7 +583,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
     s->npar = 2;
   }
   hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_merged[0],
-                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last};
+                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last, &s->ev_bip};
   for (hipEvent_t* e : evs)
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
   const size_t s1b = (size_t)(s->Bp + 1) * 8, m2b = (size_t)s->Bp * s->Bp * 8;
@@ -551,17 +609,23 @@ extern "C" rx_status rx_destroy(rx_stream* s) {
   if (!s) return RX_OK;
   if (s->magic != kMagic) return fail(RX_E_STATE, "stream handle is not live");
   (void)hipSetDevice(s->dev);
-  (void)sync_all(s);
   if (s->srv) {
+    // under the server's lock: its queued blocks leave the queue before the
+    // request loop can launch them, then the launched ones are waited for
     rx_server* srv = s->srv;
     std::lock_guard<std::mutex> lk(srv->mu);
     for (auto it = srv->queue.begin(); it != srv->queue.end();) it = (it->s == s) ? srv->queue.erase(it) : it + 1;
     for (auto& f : srv->inflight)
       for (auto& it : f.items)
         if (it.first == s) it.first = nullptr;
+    (void)sync_all(s);
     srv->used -= s->footprint;
     srv->n_streams -= 1;
+    free_stream(s);
+    delete s;
+    return RX_OK;
   }
+  (void)sync_all(s);
   free_stream(s);
   delete s;
   return RX_OK;
@@ -698,6 +762,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   const int q = s->par;                     // parity set of this batch's buffers
   j.par = q;
   d.shift = static_cast<double*>(s->shift.p);
+  d.sscale = static_cast<float*>(s->sscale.p);
   d.part = s->part.p;
   d.psum = static_cast<double*>(s->psum.p);
   d.mu_snap = static_cast<double*>(s->mu[q].p);
@@ -720,6 +785,8 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.iscale = static_cast<float*>(s->isc[q].p);
   d.oscale = static_cast<float*>(s->osc[q].p);
   d.status = static_cast<int*>(s->status[q].p);
+  d.lfac = static_cast<double*>(s->lfac[q].p);
+  d.lf_stride = lf_stride_for(s->Bp);
   d.clipflag = d.status + nblk + s->causal;
   // causal: copy the previous batch's last slot (two parity sets, so this
   // batch's merge and factor cannot overwrite it) or else form slot nblk here
@@ -818,10 +885,22 @@ static rx_status prof_collect(rx_stream* s) {
 struct Queues {
   hipStream_t A, B, C;
 };
-static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof = nullptr) {
+// Events that order the three queues of a pipelined launch: those of an
+// unserved stream (par = the batch's parity set) or of a server (par = the
+// step's parity: a served stream's two parity sets alternate per block, so
+// the previous use of a set by any stream in the step is at least two steps
+// back, and the whitening of step n - 2 has then read it).
+struct Pipe {
+  hipEvent_t* ev_merged;   // [2]
+  hipEvent_t ev_fact;
+  hipEvent_t* ev_white;    // [2]
+  int par;
+  bool causal_copy;        // a causal stream whose next batch copies this batch's last slot
+};
+static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, rx_stream* prof = nullptr) {
   const bool piped = qs.A != qs.C;
-  rx_stream* ps = piped ? jobs[0].s : nullptr;
-  if (piped && jobs.size() != 1) return fail(RX_E_STATE, "pipelined launch of several jobs");
+  rx_stream* ps = piped && jobs.size() == 1 ? jobs[0].s : nullptr;   // a lone stream's input event
+  if (piped && !pe) return fail(RX_E_STATE, "internal: pipelined launch without its events");
   auto run_groups = [&](auto key, auto launch) -> rx_status {
     std::vector<bool> done(jobs.size(), false);
     for (size_t a = 0; a < jobs.size(); ++a) {
@@ -862,7 +941,7 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
         ++cs.nb;
       }
     if (cs.nb > 0) {
-      if (piped) HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+      if (piped) HIPC(hipStreamWaitEvent(qs.C, pe->ev_fact, 0));
       HIPC(rxk_launch_copy_slot(&cs, cs.nb, qs.C));
     }
   }
@@ -878,13 +957,13 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                                return prof_mark(prof, 4, false, qs.C);
                              });
     if (r != RX_OK) return r;
-    if (piped) HIPC(hipEventRecord(ps->ev_white[jobs[0].par], qs.C));
+    if (piped) HIPC(hipEventRecord(pe->ev_white[pe->par], qs.C));
     return RX_OK;
   };
   // a one-block causal batch whitens with the copied slot only: it needs the
   // input, not this batch's statistics, so it is queued first (its scores do
   // not wait behind the host time of the statistics launches)
-  const bool early = piped && jobs[0].fast;
+  const bool early = ps && jobs[0].fast;
   if (early) {
     HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
     rx_status r0 = whiten_all();
@@ -899,7 +978,7 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                              if (it != RX_IN_U16) {        // validity pass first (float input)
                                // valid[par] is read by the whitening of the batch
                                // that last used this parity: wait for it first
-                               if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par], 0));
+                               if (piped) HIPC(hipStreamWaitEvent(qs.A, pe->ev_white[pe->par], 0));
                                const int n0 = fill(a, grp, g0, g1, &Job::wg_valid);
                                HIPC(rxk_launch_stats(it, sp, 3, &a, n0, nullptr, 0, qs.A));
                              }
@@ -912,17 +991,17 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                              if ((q = prof_mark(prof, 1, true, qs.A)) != RX_OK) return q;
                              HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, qs.A));
                              if ((q = prof_mark(prof, 1, false, qs.A)) != RX_OK) return q;
-                             if (piped) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par], 0));
+                             if (piped) HIPC(hipStreamWaitEvent(qs.A, pe->ev_white[pe->par], 0));
                              // causal: the latest whitening (and the copy before it) read
                              // the other parity's last slot, which this merge's successor
                              // overwrites; waiting here keeps one batch between them
-                             if (piped && ps->causal) HIPC(hipStreamWaitEvent(qs.A, ps->ev_white[jobs[0].par ^ 1], 0));
+                             if (piped && pe->causal_copy) HIPC(hipStreamWaitEvent(qs.A, pe->ev_white[pe->par ^ 1], 0));
                              if ((q = prof_mark(prof, 2, true, qs.A)) != RX_OK) return q;
                              HIPC(rxk_launch_stats(it, sp, 2, &c, n3, &e, n4, qs.A));
                              if ((q = prof_mark(prof, 2, false, qs.A)) != RX_OK) return q;
                              if (piped) {
-                               HIPC(hipEventRecord(ps->ev_merged[jobs[0].par], qs.A));
-                               HIPC(hipStreamWaitEvent(qs.B, ps->ev_merged[jobs[0].par], 0));
+                               HIPC(hipEventRecord(pe->ev_merged[pe->par], qs.A));
+                               HIPC(hipStreamWaitEvent(qs.B, pe->ev_merged[pe->par], 0));
                              }
                              return RX_OK;
                            });
@@ -940,8 +1019,8 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, rx_stream* prof 
                  });
   if (r != RX_OK) return r;
   if (piped) {
-    HIPC(hipEventRecord(ps->ev_fact, qs.B));
-    if (!early) HIPC(hipStreamWaitEvent(qs.C, ps->ev_fact, 0));
+    HIPC(hipEventRecord(pe->ev_fact, qs.B));
+    if (!early) HIPC(hipStreamWaitEvent(qs.C, pe->ev_fact, 0));
   }
   return early ? RX_OK : whiten_all();
 }
@@ -994,6 +1073,8 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
   // every allocation of the push happens here, before the stream changes
   const auto batches = plan_batches(blks);
   if ((r = reserve_batches(s, blks, batches)) != RX_OK) return r;
+  const bool bip = s->cfg.layout == RX_BIP;
+  if (bip && (r = dev_ensure(s->bip, bytes, s)) != RX_OK) return r;
   // A one-block device push to an idle stream (every earlier push done) runs
   // on one queue: no cross-queue handoffs, the lowest latency for a lone
   // block.  Other pushes go over the three queues, so that consecutive
@@ -1015,6 +1096,13 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     HIPC(hipEventRecord(s->ev_in, static_cast<hipStream_t>(hip_stream)));
     HIPC(hipStreamWaitEvent(qs.A, s->ev_in, 0));     // queues B and C follow A by events
   }
+  if (bip) {
+    // BIP lines -> the BIL copy, once the previous push has stopped reading it
+    HIPC(hipStreamWaitEvent(qs.A, s->ev_bip, 0));
+    HIPC(rxk_launch_bip_to_bil(x, s->bip.p, n_lines, s->B, s->S, (int)s->esz, qs.A));
+    x = s->bip.p;
+    if (is_device_ptr) HIPC(hipEventRecord(s->ev_in, qs.A));   // the fast causal path waits for the copy
+  }
   bool notready = false;
   for (const auto& bt : batches) {
     const size_t i = bt.first, k = bt.second;
@@ -1022,9 +1110,11 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready, true)) != RX_OK) { s->broken = true; return r; }
     // (float input: the whitening also reads the validity pass's output)
     jobs[0].fast = jobs[0].copy && k - i == 1 && is_device_ptr && !one_queue && s->in_type == RX_IN_U16;
-    if ((r = launch_jobs(jobs, qs, s)) != RX_OK) { s->broken = true; return r; }
+    const Pipe pe{s->ev_merged, s->ev_fact, s->ev_white, jobs[0].par, s->causal != 0};
+    if ((r = launch_jobs(jobs, qs, &pe, s)) != RX_OK) { s->broken = true; return r; }
   }
   if (!is_device_ptr) HIPC(hipEventRecord(s->ev_stage, s->st));   // last reader of the staging buffer
+  if (bip) HIPC(hipEventRecord(s->ev_bip, s->st));                 // last reader of the BIL copy
   HIPC(hipEventRecord(s->ev_last, s->st));
   s->st_only_tail = one_queue;
   s->lines_seen += n_lines;
@@ -1056,6 +1146,7 @@ static rx_status pop_scores(rx_stream* s, void* out, int want_f64, int64_t max_p
                             int32_t out_is_device, void* hip_stream) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!n_written || (!out && max_px > 0) || max_px < 0) return fail(RX_E_ARG, "bad output arguments");
   HIPC(hipSetDevice(s->dev));
   const int64_t n = std::min(max_px, s->tail - s->head);
@@ -1135,6 +1226,7 @@ extern "C" rx_status rx_encode(rx_stream* s, uint16_t* codes, int64_t max_px, in
                                void* hip_stream) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!n_px) return fail(RX_E_ARG, "null n_px");
   if (!max_out || !aligned4(max_out)) return fail(RX_E_ARG, "max_out must be a 4-byte aligned device pointer");
   HIPC(hipSetDevice(s->dev));
@@ -1153,6 +1245,7 @@ extern "C" rx_status rx_mask(rx_stream* s, double tau, int32_t mode, int64_t k, 
                              int64_t* n_px, int32_t out_is_device, void* hip_stream) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!n_px) return fail(RX_E_ARG, "null n_px");
   if (mode < RX_THR_ABS || mode > RX_THR_TOPK) return fail(RX_E_ARG, "bad threshold mode");
   if (mode == RX_THR_TOPK && k < 0) return fail(RX_E_ARG, "k must be >= 0");
@@ -1192,6 +1285,7 @@ extern "C" rx_status rx_mask_noalloc(rx_stream* s, double tau, int32_t mode, int
                                      int64_t max_bytes, int64_t* n_px, void* hip_stream) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!n_px) return fail(RX_E_ARG, "null n_px");
   if (mode < RX_THR_ABS || mode > RX_THR_TOPK) return fail(RX_E_ARG, "bad threshold mode");
   if (mode == RX_THR_TOPK && k < 0) return fail(RX_E_ARG, "k must be >= 0");
@@ -1230,7 +1324,7 @@ extern "C" rx_status rx_mask_noalloc(rx_stream* s, double tau, int32_t mode, int
 static rx_status refresh_counters(rx_stream* s) {
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
-  struct { unsigned ns, nr; unsigned long long bad, clip; } c{};
+  struct { unsigned ns, nr; unsigned long long bad, clip, sclip; } c{};
   HIPC(hipMemcpy(&c, s->nsing.p, sizeof c, hipMemcpyDeviceToHost));
   double n = 0.0;
   HIPC(hipMemcpy(&n, static_cast<double*>(s->s1[s->cur].p) + s->Bp, sizeof n, hipMemcpyDeviceToHost));
@@ -1241,6 +1335,7 @@ static rx_status refresh_counters(rx_stream* s) {
   s->cnt.notready_blocks = c.nr;
   s->cnt.nonfinite_px = (int64_t)c.bad;
   s->cnt.fp8_saturated = (int64_t)c.clip;
+  s->cnt.fp8_syrk_saturated = (int64_t)c.sclip;
   s->cnt.pending_px = s->tail - s->head;
   s->cnt.window_px = (int64_t)n;
   return RX_OK;
@@ -1249,6 +1344,7 @@ static rx_status refresh_counters(rx_stream* s) {
 extern "C" rx_status rx_wait(rx_stream* s, void* hip_stream) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   HIPC(hipSetDevice(s->dev));
   HIPC(hipEventRecord(s->ev_done, s->st));
   HIPC(hipStreamWaitEvent(static_cast<hipStream_t>(hip_stream), s->ev_done, 0));
@@ -1258,6 +1354,7 @@ extern "C" rx_status rx_wait(rx_stream* s, void* hip_stream) {
 extern "C" rx_status rx_sync(rx_stream* s) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if ((r = refresh_counters(s)) != RX_OK) return r;
   const rx_status st = s->sticky;
   s->sticky = RX_OK;
@@ -1268,6 +1365,7 @@ extern "C" rx_status rx_sync(rx_stream* s) {
 extern "C" rx_status rx_get_counters(rx_stream* s, rx_counters* out) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!out) return fail(RX_E_ARG, "null counters");
   if ((r = refresh_counters(s)) != RX_OK) return r;
   *out = s->cnt;
@@ -1279,6 +1377,7 @@ extern "C" const char* rx_last_error(void) { return g_err.c_str(); }
 extern "C" rx_status rx_profile(rx_stream* s, int32_t enable) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
   if ((r = prof_collect(s)) != RX_OK) return r;
@@ -1290,6 +1389,7 @@ extern "C" rx_status rx_profile(rx_stream* s, int32_t enable) {
 extern "C" rx_status rx_phase_times(rx_stream* s, double* ms, int64_t* launches) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!ms || !launches) return fail(RX_E_ARG, "null output");
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
@@ -1301,6 +1401,7 @@ extern "C" rx_status rx_phase_times(rx_stream* s, double* ms, int64_t* launches)
 extern "C" rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double* cov) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!n) return fail(RX_E_ARG, "null n");
   HIPC(hipSetDevice(s->dev));
   HIPC(sync_all(s));
@@ -1323,6 +1424,7 @@ extern "C" rx_status rx_get_stats(rx_stream* s, int64_t* n, double* mean, double
 extern "C" rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, const double* cov) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (n < 0 || (n > 0 && (!mean || !cov))) return fail(RX_E_ARG, "bad statistics");
   if (n > 0 && n <= s->cfg.ddof) return fail(RX_E_ARG, "n must exceed ddof");
   HIPC(hipSetDevice(s->dev));
@@ -1346,6 +1448,7 @@ extern "C" rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, c
 extern "C" rx_status rx_get_whitener(rx_stream* s, double* w) {
   rx_status r = check_stream(s);
   if (r != RX_OK) return r;
+  SrvLock held(s);
   if (!w) return fail(RX_E_ARG, "null output");
   if (s->last_w_off < 0) return fail(RX_E_STATE, "no block has been factored yet");
   HIPC(hipSetDevice(s->dev));
@@ -1360,6 +1463,19 @@ extern "C" rx_status rx_get_whitener(rx_stream* s, double* w) {
 }
 
 // ---------------------------------------------------------------------------- server
+static void free_server(rx_server* srv) {
+  for (auto& f : srv->inflight) srv->free_events.push_back(f.ev);
+  for (hipEvent_t e : srv->free_events) (void)hipEventDestroy(e);
+  hipEvent_t evs[] = {srv->ev_merged[0], srv->ev_merged[1], srv->ev_fact, srv->ev_white[0], srv->ev_white[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (srv->st) (void)hipStreamDestroy(srv->st);
+  if (srv->stA) (void)hipStreamDestroy(srv->stA);
+  if (srv->stB) (void)hipStreamDestroy(srv->stB);
+  srv->magic = 0;
+  delete srv;
+}
+
 extern "C" rx_status rx_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32_t device, rx_server** out) {
   if (!out) return fail(RX_E_ARG, "null output handle");
   *out = nullptr;
@@ -1372,25 +1488,40 @@ extern "C" rx_status rx_server_create(size_t hbm_budget_bytes, int32_t max_strea
   srv->budget = hbm_budget_bytes;
   srv->max_streams = max_streams;
   srv->dev = device;
-  if (hipStreamCreateWithFlags(&srv->st, hipStreamNonBlocking) != hipSuccess) {
-    delete srv;
+  if (hipStreamCreateWithFlags(&srv->st, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&srv->stA, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&srv->stB, hipStreamNonBlocking) != hipSuccess) {
+    free_server(srv);
     return fail(RX_E_DEVICE, "hipStreamCreate failed");
   }
+  hipEvent_t* evs[] = {&srv->ev_merged[0], &srv->ev_merged[1], &srv->ev_fact, &srv->ev_white[0], &srv->ev_white[1]};
+  for (hipEvent_t* e : evs)
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+      free_server(srv);
+      return fail(RX_E_DEVICE, "hipEventCreate failed");
+    }
+  // the parity events start out recorded (nothing to wait for)
+  for (int q = 0; q < 2; ++q)
+    if (hipEventRecord(srv->ev_white[q], srv->st) != hipSuccess) {
+      free_server(srv);
+      return fail(RX_E_DEVICE, "hipEventRecord failed");
+    }
   *out = srv;
   return RX_OK;
 }
+
+static rx_status stop_loop(rx_server* srv);
 
 extern "C" rx_status rx_server_destroy(rx_server* srv) {
   if (!srv) return RX_OK;
   if (srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
   (void)hipSetDevice(srv->dev);
   if (srv->n_streams > 0) return fail(RX_E_STATE, "destroy the server's %d streams first", srv->n_streams);
+  (void)stop_loop(srv);
   (void)hipStreamSynchronize(srv->st);
-  for (auto& f : srv->inflight) srv->free_events.push_back(f.ev);
-  for (hipEvent_t e : srv->free_events) (void)hipEventDestroy(e);
-  (void)hipStreamDestroy(srv->st);
-  srv->magic = 0;
-  delete srv;
+  (void)hipStreamSynchronize(srv->stA);
+  (void)hipStreamSynchronize(srv->stB);
+  free_server(srv);
   return RX_OK;
 }
 
@@ -1403,23 +1534,27 @@ extern "C" rx_status rx_server_submit(rx_server* srv, rx_stream* s, const void* 
   if (!lines_dev || n_lines < 1) return fail(RX_E_ARG, "bad block");
   const int mbl = s->cfg.block_lines > 0 ? s->cfg.block_lines : 128;
   if (n_lines > mbl) return fail(RX_E_ARG, "block of %lld lines exceeds the stream's %d", (long long)n_lines, mbl);
-  std::lock_guard<std::mutex> lk(srv->mu);
-  // the block starts where the stream's queued blocks end: it must end at or
-  // before the next window edge (refused here, so a step never meets it)
-  const int64_t R = s->cfg.window_lines, pos = s->lines_seen + s->q_lines;
-  if (R > 0 && pos % R + n_lines > R)
-    return fail(RX_E_ARG, "block of %lld lines at line %lld straddles a window edge (every %lld lines)",
-                (long long)n_lines, (long long)pos, (long long)R);
-  srv->queue.push_back(Pending{s, lines_dev, n_lines, tag});
-  s->q_lines += n_lines;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    // the block starts where the stream's queued blocks end: it must end at or
+    // before the next window edge (refused here, so a step never meets it)
+    const int64_t R = s->cfg.window_lines, pos = s->lines_seen + s->q_lines;
+    if (R > 0 && pos % R + n_lines > R)
+      return fail(RX_E_ARG, "block of %lld lines at line %lld straddles a window edge (every %lld lines)",
+                  (long long)n_lines, (long long)pos, (long long)R);
+    srv->queue.push_back(Pending{s, lines_dev, n_lines, tag});
+    s->q_lines += n_lines;
+  }
+  srv->cv.notify_one();
   return RX_OK;
 }
 
-extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
-  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+// One batched step: the oldest queued block of every stream that has one,
+// launched over the server's three queues (with the lock held).  Queue A
+// runs the statistics of this step while queues B and C still run the
+// factorisation and whitening of the previous one.
+static rx_status step_locked(rx_server* srv, int32_t* n_blocks) {
   if (n_blocks) *n_blocks = 0;
-  HIPC(hipSetDevice(srv->dev));
-  std::lock_guard<std::mutex> lk(srv->mu);
   // one block per stream per step (a stream's blocks depend on each other):
   // the oldest queued block of each stream, left in the queue until every
   // allocation of the step has succeeded
@@ -1461,7 +1596,8 @@ extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
     s->cnt.lines_pushed += take[i].lines;
     f.items.push_back({s, take[i].tag});
   }
-  rx_status r = launch_jobs(jobs, Queues{srv->st, srv->st, srv->st});
+  const Pipe pe{srv->ev_merged, srv->ev_fact, srv->ev_white, srv->spar, false};
+  rx_status r = launch_jobs(jobs, Queues{srv->stA, srv->stB, srv->st}, &pe);
   if (r == RX_OK && srv->free_events.empty()) {
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) r = fail(RX_E_DEVICE, "hipEventCreate failed");
@@ -1477,20 +1613,26 @@ extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
     for (auto& t : take) t.s->broken = true;
     return r;
   }
+  srv->spar ^= 1;
   srv->inflight.push_back(std::move(f));
+  srv->loop_steps += 1;
   if (n_blocks) *n_blocks = (int32_t)take.size();
   return RX_OK;
 }
 
-extern "C" rx_status rx_server_poll(rx_server* srv, uint64_t* tags, int32_t max_tags, int32_t* n_done, int32_t block) {
+extern "C" rx_status rx_server_step(rx_server* srv, int32_t* n_blocks) {
   if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
-  if (!n_done || (!tags && max_tags > 0)) return fail(RX_E_ARG, "bad output arguments");
+  if (n_blocks) *n_blocks = 0;
   HIPC(hipSetDevice(srv->dev));
   std::lock_guard<std::mutex> lk(srv->mu);
-  int32_t n = 0;
+  if (srv->running) return fail(RX_E_STATE, "the server's request loop is running; it steps by itself");
+  return step_locked(srv, n_blocks);
+}
+
+// Move finished steps (in launch order) to the done list; block: wait for all.
+static rx_status collect_locked(rx_server* srv, bool block, int64_t stamp) {
   while (!srv->inflight.empty()) {
     InFlight& f = srv->inflight.front();
-    if ((int32_t)(n + f.items.size()) > max_tags) break;
     if (block) {
       HIPC(hipEventSynchronize(f.ev));
     } else {
@@ -1498,17 +1640,119 @@ extern "C" rx_status rx_server_poll(rx_server* srv, uint64_t* tags, int32_t max_
       if (q == hipErrorNotReady) break;
       if (q != hipSuccess) return fail(RX_E_DEVICE, "hipEventQuery: %s", hipGetErrorString(q));
     }
-    for (auto& it : f.items) tags[n++] = it.second;
+    const int64_t t = stamp ? clock_ns() : 0;
+    for (auto& it : f.items) srv->done.push_back(Done{it.second, t});
     srv->free_events.push_back(f.ev);
     srv->inflight.pop_front();
   }
-  *n_done = n;
   return RX_OK;
+}
+
+// The persistent request loop: launch a step whenever blocks are queued and
+// fewer than kLoopDepth steps are in flight (blocks arriving meanwhile join
+// the next step), and stamp finished steps as soon as their event completes.
+static constexpr size_t kLoopDepth = 2;
+static void loop_main(rx_server* srv) {
+  (void)hipSetDevice(srv->dev);
+  std::unique_lock<std::mutex> lk(srv->mu);
+  while (!srv->stop) {
+    bool progress = false;
+    const size_t before = srv->done.size();
+    rx_status r = collect_locked(srv, false, true);
+    if (r == RX_OK && srv->inflight.size() < kLoopDepth && !srv->queue.empty()) {
+      int32_t nb = 0;
+      r = step_locked(srv, &nb);
+      progress = nb > 0;
+    }
+    if (r != RX_OK && srv->loop_err == RX_OK) {
+      srv->loop_err = r;
+      srv->loop_msg = g_err;
+    }
+    progress |= srv->done.size() != before;
+    if (!progress) {
+      // nothing to launch: sleep until a submission or a short poll period
+      // (completions are stamped within about that period)
+      srv->cv.wait_for(lk, std::chrono::microseconds(srv->inflight.empty() ? 2000 : 20));
+    }
+  }
+}
+
+extern "C" rx_status rx_server_start(rx_server* srv) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (srv->running) return fail(RX_E_STATE, "the request loop is already running");
+  srv->stop = false;
+  srv->loop_err = RX_OK;
+  srv->running = true;
+  try {
+    srv->loop = std::thread(loop_main, srv);
+  } catch (...) {
+    srv->running = false;
+    return fail(RX_E_STATE, "could not start the request loop thread");
+  }
+  return RX_OK;
+}
+
+static rx_status stop_loop(rx_server* srv) {
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (!srv->running) return RX_OK;
+    srv->stop = true;
+  }
+  srv->cv.notify_all();
+  srv->loop.join();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->running = false;
+  if (srv->loop_err != RX_OK) return fail(srv->loop_err, "request loop: %s", srv->loop_msg.c_str());
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_stop(rx_server* srv) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  return stop_loop(srv);
+}
+
+extern "C" int64_t rx_clock_ns(void) { return clock_ns(); }
+
+extern "C" rx_status rx_server_poll_ns(rx_server* srv, uint64_t* tags, int64_t* done_ns, int32_t max_tags,
+                                       int32_t* n_done, int32_t block) {
+  if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
+  if (!n_done || (!tags && max_tags > 0)) return fail(RX_E_ARG, "bad output arguments");
+  *n_done = 0;
+  HIPC(hipSetDevice(srv->dev));
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (!srv->running || block) {
+    rx_status r = collect_locked(srv, block && !srv->running, srv->running);
+    if (r != RX_OK) return r;
+    if (block && srv->running)                 // the loop collects: wait until it has everything
+      while (!srv->inflight.empty() || !srv->queue.empty()) {
+        if (srv->loop_err != RX_OK) return fail(srv->loop_err, "request loop: %s", srv->loop_msg.c_str());
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        lk.lock();
+      }
+  }
+  int32_t n = 0;
+  while (!srv->done.empty() && n < max_tags) {
+    tags[n] = srv->done.front().tag;
+    if (done_ns) done_ns[n] = srv->done.front().t_ns;
+    srv->done.pop_front();
+    ++n;
+  }
+  *n_done = n;
+  if (srv->loop_err != RX_OK) return fail(srv->loop_err, "request loop: %s", srv->loop_msg.c_str());
+  return RX_OK;
+}
+
+extern "C" rx_status rx_server_poll(rx_server* srv, uint64_t* tags, int32_t max_tags, int32_t* n_done, int32_t block) {
+  return rx_server_poll_ns(srv, tags, nullptr, max_tags, n_done, block);
 }
 
 extern "C" rx_status rx_server_sync(rx_server* srv) {
   if (!srv || srv->magic != 0x52585356u) return fail(RX_E_STATE, "server handle is not live");
   HIPC(hipSetDevice(srv->dev));
+  HIPC(hipStreamSynchronize(srv->stA));
+  HIPC(hipStreamSynchronize(srv->stB));
   HIPC(hipStreamSynchronize(srv->st));
   return RX_OK;
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "librx.so")
 
 RX_OK, RX_E_ARG, RX_E_NOMEM, RX_E_NOTREADY, RX_E_SINGULAR, RX_E_DEVICE, RX_E_BUDGET, RX_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 RX_IN_U16, RX_IN_F32, RX_IN_F64 = 0, 1, 2
-RX_BIL = 0
+RX_BIL, RX_BIP = 0, 1
 RX_FP64, RX_FP32, RX_BF16, RX_FP16, RX_FP8_E4M3 = 0, 1, 2, 3, 4
 RX_THR_ABS, RX_THR_REL_MAX, RX_THR_TOPK = 0, 1, 2
 RX_FLAG_CAUSAL = 1
@@ -36,7 +36,7 @@ EXPORTED = [
     "rx_get_whitener", "rx_server_create", "rx_server_destroy", "rx_stream_footprint", "rx_server_submit",
     "rx_server_step", "rx_server_poll", "rx_server_sync", "rx_server_queued", "rx_profile",
     "rx_phase_times", "rx_tx_encode", "rx_tx_decode", "rx_encode", "rx_bin_bands", "rx_split_plan",
-    "rx_mask_noalloc",
+    "rx_mask_noalloc", "rx_server_start", "rx_server_stop", "rx_server_poll_ns", "rx_clock_ns",
 ]
 
 
@@ -52,7 +52,7 @@ class rx_config(C.Structure):
 class rx_counters(C.Structure):
     _fields_ = [("lines_pushed", C.c_int64), ("blocks", C.c_int64), ("singular_blocks", C.c_int64),
                 ("notready_blocks", C.c_int64), ("pending_px", C.c_int64), ("window_px", C.c_int64),
-                ("nonfinite_px", C.c_int64), ("fp8_saturated", C.c_int64)]
+                ("nonfinite_px", C.c_int64), ("fp8_saturated", C.c_int64), ("fp8_syrk_saturated", C.c_int64)]
 
 
 class RxError(RuntimeError):
@@ -108,6 +108,10 @@ def _load():
         "rx_bin_bands": (I32, [P, I64, I32, I32, I32, I32, I32, I32, P, P]),
         "rx_split_plan": (I32, [C.POINTER(rx_config), I64, C.POINTER(I32), C.POINTER(I64)]),
         "rx_mask_noalloc": (I32, [P, D, I32, I64, P, I64, C.POINTER(I64), P]),
+        "rx_server_start": (I32, [P]),
+        "rx_server_stop": (I32, [P]),
+        "rx_server_poll_ns": (I32, [P, P, P, I32, C.POINTER(I32), I32]),
+        "rx_clock_ns": (I64, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -147,7 +151,8 @@ def _stream_handle(stream) -> int:
 
 
 def make_config(bands: int, samples: int, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ddof=0,
-                ridge_rel=0.0, block_lines=0, window_lines=0, bit_depth=12, device=0, causal=False) -> rx_config:
+                ridge_rel=0.0, block_lines=0, window_lines=0, bit_depth=12, device=0, causal=False,
+                layout=RX_BIL) -> rx_config:
     cfg = rx_config()
     check(LIB.rx_config_init(C.byref(cfg), bands, samples))
     cfg.in_type = IN_TYPE[np.dtype(in_dtype)]
@@ -157,6 +162,7 @@ def make_config(bands: int, samples: int, in_dtype=np.uint16, syrk="bf16", white
     cfg.ddof, cfg.ridge_rel = ddof, float(ridge_rel)
     cfg.block_lines, cfg.window_lines, cfg.device = block_lines, window_lines, device
     cfg.flags = RX_FLAG_CAUSAL if causal else 0
+    cfg.layout = layout
     return cfg
 
 
@@ -173,7 +179,8 @@ class RxStream:
 
     # -- core path
     def rx_push_lines(self, lines, stream=None, allow_notready=True, guard=True) -> int:
-        """lines: BIL [n_lines][B][S] torch tensor (device or host) or numpy array.
+        """lines: BIL [n_lines][B][S] (BIP [n_lines][S][B] for an RX_BIP stream)
+        torch tensor (device or host) or numpy array.
 
         A device tensor is read asynchronously on the library's own queues,
         after the work already on the caller's stream (torch's current one by
@@ -185,7 +192,8 @@ class RxStream:
         push): the tensor must then stay alive and unchanged until rx_sync or
         an rx_wait, as the C interface states."""
         n = lines.shape[0]
-        assert tuple(lines.shape[1:]) == (self.B, self.S), lines.shape
+        shape = (self.S, self.B) if self.cfg.layout == RX_BIP else (self.B, self.S)
+        assert tuple(lines.shape[1:]) == shape, lines.shape
         dev = _is_dev(lines)
         sh = _stream_handle(stream) if dev else 0
         r = check(LIB.rx_push_lines(self.h, _ptr(lines), n, dev, sh),
@@ -315,6 +323,20 @@ class RxServer:
     def rx_server_sync(self):
         check(LIB.rx_server_sync(self.h))
 
+    def rx_server_start(self):
+        check(LIB.rx_server_start(self.h))
+
+    def rx_server_stop(self):
+        check(LIB.rx_server_stop(self.h))
+
+    def rx_server_poll_ns(self, block: bool = False, max_tags: int = 4096):
+        """Finished blocks as (tags, completion stamps in ns of clock_ns())."""
+        tags = np.zeros(max_tags, dtype=np.uint64)
+        ts = np.zeros(max_tags, dtype=np.int64)
+        n = C.c_int32()
+        check(LIB.rx_server_poll_ns(self.h, tags.ctypes.data, ts.ctypes.data, max_tags, C.byref(n), int(block)))
+        return tags[: n.value].tolist(), ts[: n.value].tolist()
+
     def rx_server_queued(self):
         q, f, u = C.c_int32(), C.c_int32(), C.c_size_t()
         check(LIB.rx_server_queued(self.h, C.byref(q), C.byref(f), C.byref(u)))
@@ -360,3 +382,8 @@ def split_plan(cfg: rx_config, lines: int):
     ks, mc = C.c_int32(0), C.c_int64(0)
     check(LIB.rx_split_plan(C.byref(cfg), lines, C.byref(ks), C.byref(mc)))
     return ks.value, mc.value
+
+
+def clock_ns() -> int:
+    """The library's monotonic clock (ns), the time base of rx_server_poll_ns."""
+    return int(LIB.rx_clock_ns())

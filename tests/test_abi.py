@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2602_13509_amd", "librx.so")
 
 def declared():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:rx_status|const char\*)\s+(rx_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:rx_status|const char\*|int64_t)\s+(rx_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_core_calls():
@@ -45,8 +45,8 @@ def test_config_defaults_and_host_validation():
     assert (cfg.in_type, cfg.syrk_prec, cfg.whiten_prec, cfg.bit_depth) == (rx.RX_IN_U16, rx.RX_BF16, rx.RX_BF16, 12)
     b = C.c_size_t()
     assert rx.LIB.rx_stream_footprint(C.byref(cfg), 100, C.byref(b)) == rx.RX_OK and b.value > 0
-    for field, bad in (("bands", 0), ("bands", 321), ("samples", 0), ("syrk_prec", rx.RX_FP8_E4M3),
-                       ("whiten_prec", 9), ("ddof", 2), ("layout", 1), ("flags", 2), ("struct_size", 4)):
+    for field, bad in (("bands", 0), ("bands", 321), ("samples", 0), ("syrk_prec", 5),
+                       ("whiten_prec", 9), ("ddof", 2), ("layout", 2), ("flags", 2), ("struct_size", 4)):
         c2 = rx.rx_config()
         C.memmove(C.byref(c2), C.byref(cfg), C.sizeof(cfg))
         setattr(c2, field, bad)
@@ -71,7 +71,8 @@ def test_null_handles_are_rejected():
 def test_footprint_accounts_for_causal_slot_and_float_validity():
     # Host logic only (no GPU): the admission footprint grows by the causal
     # mode's extra snapshot slot and by the float-input validity buffers,
-    # and counters carry the non-finite and FP8 saturation fields.
+    # and counters carry the non-finite and FP8 saturation fields (whitening and
+    # covariance product).
     import numpy as np
     from paper_2602_13509_amd import rx
     base = rx.stream_footprint(rx.make_config(270, 640, in_dtype=np.uint16), 100)
@@ -81,4 +82,4 @@ def test_footprint_accounts_for_causal_slot_and_float_validity():
     assert flt - base >= 2 * 100 * 640               # two parity sets of one validity byte per pixel
     assert rx.make_config(16, 16, causal=True).flags == rx.RX_FLAG_CAUSAL
     names = [f[0] for f in rx.rx_counters._fields_]
-    assert names[-2:] == ["nonfinite_px", "fp8_saturated"]
+    assert names[-3:] == ["nonfinite_px", "fp8_saturated", "fp8_syrk_saturated"]

@@ -1,0 +1,73 @@
+"""Band-interleaved-by-pixel input (RX_BIP, [line][sample][band]) through
+the C ABI: the library transposes each push into BIL on the device, so the
+scores must equal those of the same lines pushed as BIL bit for bit (FP64
+and BF16 paths, device and host input, a ragged shape spanning several
+transpose tiles, several pushes and blocks, causal scoring), and match the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_scores, oracle_stream_scores, say
+from paper_2602_13509_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rxm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2602_13509_amd import rx
+    return rx
+
+
+def _run(rxm, cube, layout, prec, device, pushes, **kw):
+    import torch
+    B, S = cube.shape[1], cube.shape[2]
+    cfg = rxm.make_config(B, S, in_dtype=cube.dtype, syrk=prec, whiten=prec,
+                          ridge_rel=1e-6 if prec == "bf16" else 0.0, layout=layout, **kw)
+    st = rxm.RxStream(cfg)
+    data = cube if layout == rxm.RX_BIL else np.ascontiguousarray(cube.transpose(0, 2, 1))
+    l0 = 0
+    for n in pushes:
+        part = np.ascontiguousarray(data[l0:l0 + n])
+        st.rx_push_lines(torch.from_numpy(part).cuda() if device else part)
+        l0 += n
+    st.rx_sync()
+    out = st.scores_host(f64=(prec == "fp64"))
+    st.rx_destroy()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+@pytest.mark.parametrize("device", [True, False])
+def test_bip_scores_equal_bil_bitwise(rxm, prec, device):
+    B, S = 270, 203
+    cube = synth.sensor_cube(81, lines=30, samples=S, bands=B).cube
+    pushes = [7, 11, 12]
+    say(f"BIP vs BIL: 30x{S}x{B} u16, {prec}, {'device' if device else 'host'} input, pushes {pushes}")
+    a = _run(rxm, cube, rxm.RX_BIL, prec, device, pushes, block_lines=8)
+    b = _run(rxm, cube, rxm.RX_BIP, prec, device, pushes, block_lines=8)
+    w = np.uint64 if prec == "fp64" else np.uint32
+    assert np.array_equal(a.view(w), b.view(w))
+    ref, _ = oracle_stream_scores(cube, B, S, pushes=pushes, block_lines=8, rho=1e-6 if prec == "bf16" else 0.0)
+    tol = (1e-9, 1e-11) if prec == "fp64" else (5e-2, 1e-2)
+    assert_scores(b, ref, B, *tol, label=f"BIP {prec}")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_bip_float_and_causal(rxm, dtype):
+    B, S = 33, 70
+    cube = synth.sensor_cube(82, lines=24, samples=S, bands=B).cube.astype(dtype)
+    a = _run(rxm, cube, rxm.RX_BIL, "fp64", True, [1, 9, 14], causal=True)
+    b = _run(rxm, cube, rxm.RX_BIP, "fp64", True, [1, 9, 14], causal=True)
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_bip_refused_for_served_streams(rxm):
+    srv = rxm.RxServer(1 << 30, 2)
+    with pytest.raises(rxm.RxError) as e:
+        rxm.RxStream(rxm.make_config(16, 32, layout=rxm.RX_BIP), server=srv)
+    assert e.value.status == rxm.RX_E_ARG
+    srv.rx_server_destroy()

@@ -428,3 +428,69 @@ def test_relative_mask_maximum_over_pending_after_partial_pops(rxm):
     assert np.array_equal(st.mask_host(tau, rxm.RX_THR_REL_MAX), expect(last))
     st.rx_destroy()
     tw.rx_destroy()
+
+
+# ---------------------------------------------------------------------------- FP8 covariance product
+def _fp8_block_product_emulation(cube):
+    """Host emulation of one block's FP8 covariance operand: the shift c is
+    the first line's band mean rounded to FP32, the band scale 2^-e puts the
+    first line's largest |x - c| (FP32) at or below 224, the operand is the
+    E4M3 rounding (saturating) of (x - c) 2^-e in FP32; returns the unscaled
+    product sum_p q_a q_b / (s_a s_b) (exact in FP64), the shift, and the
+    number of values beyond the format's range."""
+    from lowp_emu import q_e4m3
+    px = orx.pixels(cube).astype(np.float32)                     # [n][B]
+    S = cube.shape[2]
+    first = px[:S].astype(np.float64)
+    c = (first.sum(axis=0) / S).astype(np.float32)
+    m = np.max(np.abs(px[:S] - c[None, :]), axis=0).astype(np.float64)
+    e = np.where(m > 0, np.frexp(m / 224.0)[1], 0)
+    sc = np.ldexp(np.float32(1.0), -e).astype(np.float32)
+    dv = (px - c[None, :]) * sc[None, :]
+    clips = int(np.sum(np.abs(dv) > 464.0))
+    q = q_e4m3(dv)
+    prod = (q.T @ q) / np.outer(sc.astype(np.float64), sc.astype(np.float64))
+    return prod, c.astype(np.float64), clips
+
+
+@pytest.mark.parametrize("samples", [64, 203])
+def test_fp8_covariance_product_matches_host_emulation(rxm, samples):
+    # One block (a single split): the kernel's window statistics must equal
+    # the emulated FP8 product with the merge's exact shift correction, to
+    # FP32 accumulation rounding (far below one FP8 step), and its
+    # saturation count must equal the emulated one.
+    B, L = 64, 20
+    cube = synth.sensor_cube(91, lines=L, samples=samples, bands=B).cube
+    prod, c, clips = _fp8_block_product_emulation(cube)
+    px = orx.pixels(cube).astype(np.float64)
+    n = px.shape[0]
+    mb = px.mean(axis=0)
+    m2 = prod - n * np.outer(mb - c, mb - c)
+    st = run_stream(rxm, cube, "fp8", "bf16", ridge_rel=1e-6)
+    nn, mu, cov = st.rx_get_stats()
+    assert nn == n
+    got = cov * n
+    scale = np.abs(prod).max()
+    err = np.max(np.abs(got - m2)) / scale
+    say(f"  fp8 covariance S={samples}: max |M2 - emulation| / max|product| = {err:.3e}; "
+        f"{st.rx_get_counters().fp8_syrk_saturated} saturated (emulation {clips})")
+    assert err <= 2.0 ** -24 * 512
+    assert st.rx_get_counters().fp8_syrk_saturated == clips
+
+
+def test_fp8_covariance_scores_reported(rxm):
+    # FP8 operands in the covariance product at 270 bands, BF16 whitening,
+    # against the oracle with the same ridge: reported, not bounded (parity
+    # unpinned for FP8, as for FP8 whitening), except that every score is
+    # finite and the implanted-material pixels stay at the top.
+    B, S = 270, 640
+    cube = synth.sensor_cube(92, lines=40, samples=S, bands=B).cube
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=20, rho=1e-6)
+    st = run_stream(rxm, cube, "fp8", "bf16", block_lines=20, ridge_rel=1e-6)
+    got = st.scores_host()
+    mx, p99 = err_summary(got, ref, B)
+    say(f"  fp8 covariance + bf16 whitening: max rel {mx:.3e}, p99 rel {p99:.3e} (reported); "
+        f"{st.rx_get_counters().fp8_syrk_saturated} saturated")
+    assert np.all(np.isfinite(got))
+    top = np.argsort(-ref)[:10]
+    assert np.all(got[top] > np.quantile(got, 0.99))

@@ -265,3 +265,58 @@ def test_straddling_submit_is_refused_and_the_server_stays_consistent(rxm):
     srv.rx_server_destroy()
     assert np.array_equal(got_a.view(np.uint32), want_a.view(np.uint32))
     assert np.array_equal(got_b.view(np.uint32), want_b.view(np.uint32))
+
+
+def test_request_loop_mix_equals_alone_bitwise(rxm):
+    # The library's own request loop (rx_server_start) steps the server while
+    # blocks are submitted from this thread in an interleaved random order,
+    # with pauses so that some steps run while others are queued.  Every
+    # block is stamped done on the library clock, after its submission; the
+    # scores equal the streams' alone runs bit for bit.
+    import time
+    import torch
+    streams = make_streams(17)
+    dcubes = [dev(c) for (_, _, _, c) in streams]
+    alone = []
+    for (B, S, blocks, cube), dc in zip(streams, dcubes):
+        st = rxm.RxStream(cfg_for(rxm, B, S, 0))
+        l0 = 0
+        for n in blocks:
+            st.rx_push_lines(dc[l0:l0 + n])
+            l0 += n
+        st.rx_sync()
+        alone.append(st.scores_host())
+        st.rx_destroy()
+    srv = rxm.RxServer(8 << 30, 16)
+    served = [rxm.RxStream(cfg_for(rxm, B, S, 64), server=srv) for (B, S, _, _) in streams]
+    order = [(i, j) for i, s in enumerate(streams) for j in range(len(s[2]))]
+    rng = np.random.default_rng(5)
+    rng.shuffle(order)
+    starts = [np.concatenate([[0], np.cumsum(s[2])]) for s in streams]
+    nxt = [0] * len(streams)
+    with pytest.raises(rxm.RxError):
+        srv.rx_server_start()
+        srv.rx_server_start()                       # already running
+    sub = {}
+    for tag, (i, _) in enumerate(order):
+        j = nxt[i]
+        nxt[i] += 1
+        sub[tag] = rxm.clock_ns()
+        srv.rx_server_submit(served[i], dcubes[i][int(starts[i][j]):int(starts[i][j + 1])], tag)
+        if tag % 4 == 3:
+            time.sleep(0.002)
+    with pytest.raises(rxm.RxError) as e:
+        srv.rx_server_step()                        # the loop steps by itself
+    assert e.value.status == rxm.RX_E_STATE
+    tags, stamps = srv.rx_server_poll_ns(block=True)
+    srv.rx_server_stop()
+    assert sorted(tags) == list(range(len(order)))
+    lat = [(t_done - sub[t]) * 1e-6 for t, t_done in zip(tags, stamps)]
+    say(f"request loop: {len(order)} blocks, latency ms p50 {np.median(lat):.3f}, max {max(lat):.3f}")
+    assert min(lat) > 0.0
+    torch.cuda.synchronize()
+    for k, ((B, S, blocks, cube), st) in enumerate(zip(streams, served)):
+        got = st.scores_host()
+        assert np.array_equal(got.view(np.uint32), alone[k].view(np.uint32)), f"stream {k} (B={B}, S={S})"
+        st.rx_destroy()
+    srv.rx_server_destroy()
