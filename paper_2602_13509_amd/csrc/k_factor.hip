@@ -1,32 +1,21 @@
 // FP64 factorisation of the window covariance for Eq. 1 of the paper
 // (Section "System Implementation / Detection Algorithm"): the score needs
 // Sigma^{-1}; it is applied as delta = |W (x - mu)|^2 with W lower
-// triangular and W^T W = (Sigma + lambda I)^{-1}.
-//
-// One 512-thread workgroup per block snapshot (causal mode adds one for the
-// window before the batch):
+// triangular and W^T W = (Sigma + lambda I)^{-1}.  Per block snapshot
+// (causal mode adds one for the window before the batch):
 //   Sigma = M2 / (N - ddof);  lambda = rho * tr(Sigma) / B;  Sigma_r = Sigma + lambda I
 //   equilibration R = S Sigma_r S with S = diag(Sigma_r,kk^{-1/2})  (unit diagonal)
-//   R = L L^T and W = L^{-1} S in one right-looking sweep over 16x16 tiles
-//   held in registers, FP64 matrix-core products (details below).
+//   R = L L^T (k_chol), W = L^{-1} S (k_trinv), FP64 matrix-core products.
 //   A non-positive pivot flags the block singular (its scores become NaN).
-// The whitening operand in the whitening precision is then formed with
-// power-of-two scales: input band scale 2^-e_k (e_k = floor(log2 sigma_k))
-// and output row scale 2^f_i chosen so each row fits the format's range.
+// The whitening operand in the whitening precision is then formed (k_wop)
+// with power-of-two scales: input band scale 2^-e_k (e_k = floor(log2
+// sigma_k)) and output row scale 2^f_i chosen so each row fits the format's
+// range.
 #include "rx_dev.h"
 
 namespace rxk {
 
 constexpr int MAXBP = 16 * MAXT;
-constexpr int FNW = 8;                  // waves per factor workgroup (2 per SIMD: 256 registers each)
-constexpr int FNT = 64 * FNW;           // threads per factor workgroup
-// tiles per wave, a template argument sized to the band count: wave 0 holds
-// the T diagonal tiles, the other waves share the T (T - 1) / 2 tiles below
-// the diagonal; up to 20 tiles (B <= 272) they and the step's temporaries fit
-// in registers
-constexpr int ftpw_for(int T) {
-  return T > (T * (T - 1) / 2 + FNW - 2) / (FNW - 1) ? T : (T * (T - 1) / 2 + FNW - 2) / (FNW - 1);
-}
 constexpr int FTS = 16 * 17;            // LDS tile: 16 rows, pitch 17 doubles (bank-conflict free)
 
 __device__ __forceinline__ double readlane_d(double x, int l) {
@@ -36,342 +25,8 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   return __builtin_bit_cast(double, v);
 }
 
-template <int WP, int FTPW>
-__global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
-  int b;
-  const int bi = find_batch(ls, blockIdx.x, b);
-  const BatchDesc& d = ls.d[bi];
-  const int B = d.B, Bp = d.Bp;
-  const int64_t bp2 = (int64_t)Bp * Bp;
-  const double* R = d.m2_snap + b * bp2;
-  double* W = d.w64 + b * bp2;
-  __shared__ double lcol[MAXT * FTS];   // pivot column: R_ik, then L_ik
-  __shared__ double prow[MAXT * FTS];   // pivot row: E_kj, then W_kj; Y at k
-  __shared__ double ybuf[2][FTS];       // Y_k = L_kk^{-1}, by step parity
-  __shared__ double sc[MAXBP];          // equilibration scale
-  __shared__ double T22[16][17];
-  __shared__ double red[FNW];
-  __shared__ int flag;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
-  const double N = d.n_snap[b];
-
-  if (tid == 0) d.clipflag[b] = 0;             // set by the whitening of this batch
-  // the block this slot scores (causal mode: slot b scores block b + 1, the
-  // extra slot nblk block 0, the last slot none in this batch); the stream's
-  // singular / not-ready counters count scored blocks
-  const int sbk = !d.causal ? b : (b == d.nblk ? 0 : (b + 1 < d.nblk ? b + 1 : -1));
-  const bool counted = sbk >= 0 && !causal_empty(d, sbk);
-  if (tid == 0 && sbk >= 0 && causal_empty(d, sbk)) atomicAdd(d.nsing + 1, 1u);   // no window before it
-  // window too small: Sigma is singular (no ridge), or its normaliser is not
-  // positive (float input whose non-finite pixels left too few)
-  if ((d.rho == 0.0 && N <= (double)B) || !(N - (double)d.ddof > 0.0)) {
-    if (tid == 0) { d.status[b] = 2; if (counted) atomicAdd(d.nsing + 1, 1u); }
-    return;
-  }
-  const double den = N - (double)d.ddof;
-  if (tid == 0) flag = 0;
-
-  // ---- trace and ridge
-  double tr = 0.0;
-  for (int k = tid; k < B; k += FNT) tr += R[(int64_t)k * Bp + k];
-  tr = wave_sum(tr);
-  if (lane == 0) red[wv] = tr;
-  __syncthreads();
-  tr = 0.0;
-  for (int i = 0; i < FNW; ++i) tr += red[i];
-  const double lam = d.rho * (tr / den) / (double)B;
-  for (int k = tid; k < Bp; k += FNT) {
-    double v = 1.0;
-    if (k < B) {
-      v = R[(int64_t)k * Bp + k] / den + lam;
-      if (!(v > 0.0) || !(v < INFINITY)) flag = 1;
-    }
-    sc[k] = 1.0 / sqrt(v);
-  }
-  __syncthreads();
-  if (flag) {
-    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
-    return;
-  }
-
-  // ---- one right-looking sweep over 16x16 tiles held in registers.  Wave 0
-  // owns the diagonal tiles (slot s holds tile (s, s)); the other waves own
-  // the tiles below the diagonal, cyclically in row-major order.  Step k, with
-  // Y_k = L_kk^{-1} already known:
-  //   P: the pivot column becomes L_ik = R_ik Y_k^T and the pivot row of the
-  //      eliminated identity becomes final rows of W = L^{-1}:
-  //      W_kj = Y_k E_kj, W_kk = Y_k; each owner forms its own tiles and
-  //      publishes them in LDS;
-  //   U: every tile below row k takes one 16x16x16 product:
-  //      j > k: R_ij -= L_ik L_jk^T   j == k: E_ik = -L_ik Y_k   j < k: E_ij -= L_ik W_kj
-  //      and wave 0, once its own updates are done, factors the new diagonal
-  //      tile (k + 1, k + 1) into Y_{k+1} while the other waves still update.
-  // Two barriers per step; each tile holds R, then L, then E, then W.
-  const int T = Bp / 16;
-  const int lr = lane & 15, lg = lane >> 4;
-  // LDS tiles are row-major with pitch 17: element (r, c) at r * 17 + c.
-  // offA: this lane's element of an A-operand (or transposed B) read, (lr, 4q + lg);
-  // offB: of a B-operand read / accumulator write, (lg + 4q, lr).  Per-step reads
-  // use these with immediate offsets (4q, 68q).
-  const int offA0 = lr * 17 + lg, offB0 = lg * 17 + lr;
-  const double rden = 1.0 / den;
-  f64x4 tl[FTPW];
-  int ti[FTPW], tj[FTPW];
-#pragma unroll
-  for (int s = 0; s < FTPW; ++s) {
-    int i = -1, j = -1;
-    if (wv == 0) {
-      if (s < T) { i = s; j = s; }
-    } else {
-      const int u = s * (FNW - 1) + (wv - 1);      // index among the tiles below the diagonal
-      if (u < T * (T - 1) / 2) {
-        i = 1;
-        while ((i + 1) * i / 2 <= u) ++i;
-        j = u - i * (i - 1) / 2;
-      }
-    }
-    ti[s] = __builtin_amdgcn_readfirstlane(i);
-    tj[s] = __builtin_amdgcn_readfirstlane(j);
-    tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-    if (ti[s] >= 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // branch-free: every lane loads a valid address, padding is selected away
-        const int row = 16 * ti[s] + lg + 4 * r, col = 16 * tj[s] + lr;
-        const bool in = (row < B) && (col < B);
-        const int hi = in ? (row >= col ? row : col) : 0, lo = in ? (row >= col ? col : row) : 0;
-        double v = R[(int64_t)hi * Bp + lo] * rden + ((row == col) ? lam : 0.0);
-        v *= sc[row] * sc[col];
-        v = in ? v : ((row == col) ? 1.0 : 0.0);
-        tl[s][r] = v;
-      }
-    }
-    if ((s & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // at most four tiles of loads in flight
-  }
-
-  // 16x16 Cholesky of the diagonal tile staged in T22 and Y = L^{-1} together,
-  // in wave 0: lane = (row i, column group cg of 4) holds S[i][4cg..4cg+3] and
-  // the eliminated identity E[i][4cg..4cg+3].  Column j: pivot d = sqrt(S[j][j]),
-  // L[i][j] = S[i][j] / d, Y[j][.] = E[j][.] / d, then S[i][k] -= L[i][j] L[k][j]
-  // (j < k <= i) and E[i][.] -= L[i][j] Y[j][.] (i > j).
-  auto diag = [&](double* yout) {
-    int i = lane & 15, cg = lane >> 4;
-    asm volatile("" : "+v"(i), "+v"(cg));    // shuffle addresses are formed per step, not hoisted
-    double v[4], y[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      v[e] = T22[i][4 * cg + e];
-      y[e] = (i == 4 * cg + e) ? 1.0 : 0.0;
-    }
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int je = j & 3, jg = j >> 2;
-      const double piv = readlane_d(v[je], j + 16 * jg);
-      bad |= !(piv > 0.0);
-      // 1/sqrt(piv): the hardware reciprocal square root, then two Newton
-      // steps (each squares the relative error), within a few ulp of the
-      // correctly rounded value and far shorter than a square root and a
-      // division on this column's critical path
-      double rd = __builtin_amdgcn_rsq(piv);
-#pragma unroll
-      for (int it = 0; it < 2; ++it) {
-        const double e = __builtin_fma(-piv * rd, rd, 1.0);
-        rd = __builtin_fma(0.5 * rd, e, rd);
-      }
-      const double lij = __shfl(v[je], i + 16 * jg, 64) * rd;
-      double lkj[4], yj[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
-        yj[e] = __shfl(y[e], j + 16 * cg, 64) * rd;
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int kk = 4 * cg + e;
-        if (kk > j && i >= kk) v[e] -= lij * lkj[e];
-        y[e] = (i == j) ? yj[e] : ((i > j) ? y[e] - lij * yj[e] : y[e]);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) yout[i * 17 + 4 * cg + e] = y[e];
-    if (lane == 0 && bad) flag = 1;
-  };
-  // wave 0 puts its diagonal tile kd into T22 (the same wave reads it back)
-  auto stage_diag = [&](int kd) {
-#pragma unroll
-    for (int s = 0; s < FTPW; ++s) {
-      if (ti[s] == kd && tj[s] == kd) {
-        double* p = &T22[0][0] + offB0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-      }
-    }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  };
-
-  // Step -1 only factors the first diagonal tile, so one copy of the
-  // diagonal code serves every step.
-  for (int k = -1; k < T && !flag; ++k) {
-    if (k >= 0) {
-      int offA = offA0, offB = offB0;
-      asm volatile("" : "+v"(offA), "+v"(offB));   // keep derived addresses inside the step
-      const double* yk = ybuf[k & 1];
-      // ---- P: pivot column L_ik = R_ik Y_k^T, pivot row W_kj = Y_k E_kj, W_kk = Y_k
-#pragma unroll
-      for (int s = 0; s < FTPW; ++s) {
-        if (tj[s] == k && ti[s] > k) {
-          // R_ik goes through this wave's LDS slot to be read in operand order
-          double* lc = lcol + ti[s] * FTS;
-          double* p = lc + offB;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-          const double* la = lc + offA;
-          const double* yb = yk + offA;
-          tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4)
-            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(la[4 * q4], yb[4 * q4], tl[s], 0, 0, 0);
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-        } else if (ti[s] == k && tj[s] >= 0 && tj[s] < k) {
-          // E_kj goes through this wave's LDS slot (each lane reads back the
-          // elements it wrote), then W_kj replaces it there
-          double* pr = prow + tj[s] * FTS;
-          double* p = pr + offB;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-          const double* ya = yk + offA;
-          const double* pb = pr + offB;
-          tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int q4 = 0; q4 < 4; ++q4)
-            tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-#pragma unroll
-          for (int r = 0; r < 4; ++r) p[68 * r] = tl[s][r];
-        } else if (ti[s] == k && tj[s] == k) {
-          const double* yb = yk + offB;
-          double* p = prow + k * FTS + offB;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            tl[s][r] = yb[68 * r];
-            p[68 * r] = tl[s][r];
-          }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      __syncthreads();
-      // ---- U: update every tile below row k
-#pragma unroll
-      for (int s = 0; s < FTPW; ++s) {
-        if (ti[s] > k) {
-          const double* la = lcol + ti[s] * FTS + offA;
-          if (tj[s] == k) tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-          if (tj[s] > k) {
-            const double* lb = lcol + tj[s] * FTS + offA;
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4)
-              tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], lb[4 * q4], tl[s], 0, 0, 0);
-          } else {
-            const double* pb = prow + tj[s] * FTS + offB;
-#pragma unroll
-            for (int q4 = 0; q4 < 4; ++q4)
-              tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-la[4 * q4], pb[68 * q4], tl[s], 0, 0, 0);
-          }
-        }
-      }
-    }
-    // wave 0: the next diagonal tile is final now; factor it
-    if (wv == 0 && k + 1 < T) {
-      stage_diag(k + 1);
-      diag(ybuf[(k + 1) & 1]);
-    }
-    __syncthreads();
-  }
-  if (flag) {
-    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
-    return;
-  }
-  // ---- W = L^{-1} S (FP64, row-major) and the whitening operand in the whitening
-  // precision, from the tiles.  Tiles above the diagonal are never written:
-  // those parts of both buffers are zeroed once when they are allocated.
-  constexpr bool LP = (WP == P_BF16 || WP == P_F16 || WP == P_FP8);
-  constexpr int top = (WP == P_FP8) ? 7 : 14;     // scaled row maximum lands in [2^top, 2^(top+1))
-  __shared__ int ek[MAXBP];
-  __shared__ int fi[MAXBP];
-  for (int k = tid; k < Bp; k += FNT) ek[k] = (LP && k < B) ? ilogb(1.0 / sc[k]) : 0;   // 2^e <= sigma_k < 2^(e+1)
-#pragma unroll
-  for (int s = 0; s < FTPW; ++s) {
-    if (ti[s] >= 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * ti[s] + lg + 4 * r, col = 16 * tj[s] + lr;
-        const double v = (row < B && col < B && col <= row) ? tl[s][r] * sc[col] : 0.0;
-        tl[s][r] = v;
-        W[(int64_t)row * Bp + col] = v;
-      }
-    }
-  }
-  if constexpr (WP != P_F64) {
-    using S = typename MM<WP>::storage;
-    const int Bw = 32 * ((Bp + 31) / 32);           // operand row pitch of this batch
-    S* wl = static_cast<S*>(d.wlp) + (int64_t)b * Bp * Bw;
-    __syncthreads();
-    constexpr int NCC = (MAXBP + 63) / 64;        // 64-column chunks of a row
-    if constexpr (LP) {
-      // row maxima of |W_ij 2^e_j|: one wave per four rows, lanes over the
-      // columns, every load of the four rows independent (the maximum is exact
-      // in any order)
-      for (int i0 = 4 * wv; i0 < Bp; i0 += 4 * FNW) {
-        double m[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < NCC; ++c) {
-          const int j = lane + 64 * c;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int i = i0 + q;
-            if (j <= i && j < B) m[q] = fmax(m[q], fabs(ldexp(W[(int64_t)i * Bp + j], ek[j])));
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          for (int o = 32; o > 0; o >>= 1) m[q] = fmax(m[q], __shfl_xor(m[q], o, 64));
-          if (lane == 0) fi[i0 + q] = (m[q] > 0.0) ? ilogb(m[q]) - top : 0;
-        }
-      }
-    } else {
-      for (int k = tid; k < Bp; k += FNT) fi[k] = 0;
-    }
-    __syncthreads();
-    for (int k = tid; k < Bp; k += FNT) {
-      d.iscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, -ek[k]);
-      d.oscale[(int64_t)b * Bp + k] = (float)ldexp(1.0, fi[k]);
-    }
-    // one wave per four rows, lanes over the columns of each row's lower tiles
-    for (int i0 = 4 * wv; i0 < Bp; i0 += 4 * FNW) {
-#pragma unroll
-      for (int c = 0; c < NCC; ++c) {
-        const int j = lane + 64 * c;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int i = i0 + q;
-          if (j < 16 * (i / 16 + 1))
-            wl[(int64_t)i * Bw + j] = to_storage<WP>((float)ldexp(W[(int64_t)i * Bp + j], ek[j] - fi[i]));
-        }
-      }
-    }
-  }
-  if (tid == 0) d.status[b] = 0;
-}
-
 // ============================================================================
-// Three-kernel factorisation (up to 272 bands, T <= 17 tiles), all FP64:
+// Three-kernel factorisation (up to 320 bands, T <= 20 tiles), all FP64:
 //   k_chol   one 1024-thread workgroup per block: conditioning (as above), then
 //            the Cholesky factor of the equilibrated R by a right-looking sweep
 //            over 16x16 tiles held in registers.  Hands over, per block, the
@@ -384,17 +39,22 @@ __global__ void __launch_bounds__(FNT) k_factor(LaunchSet ls) {
 //            four waves and added in a fixed order.
 //   k_wop    one workgroup per (block, 16-row tile): the row scales and the
 //            whitening operand of those rows (low-precision and FP32 paths).
-// The Cholesky kernel holds only R (no eliminated identity), so its tiles
-// fit the registers of 16 waves without spilling; the inverse, which is as
-// much arithmetic again, runs on T workgroups per block instead of one.
+// The Cholesky kernel holds only R (no eliminated identity): up to 272 bands
+// its tiles fit the registers of 16 waves; from 273 bands on, the tiles
+// below the diagonal past eleven per wave stay in LDS.  The inverse, which
+// is as much arithmetic again, runs on T workgroups per block instead of one.
 
 constexpr int CNW = 16;                 // waves per Cholesky workgroup (4 per SIMD: 128 registers each)
 constexpr int CNT = 64 * CNW;
 constexpr int CDW = 3;                  // waves owning the diagonal tiles (tile (k, k) -> wave k % CDW)
-constexpr int CMAXT = 17;               // largest tile count of the three-kernel path (272 bands)
-// tiles per diagonal wave and per other wave, sized to the tile count T
+constexpr int CMAXT = MAXT;             // largest tile count (320 bands)
+constexpr int CREG = 11;                // most tiles below the diagonal a wave holds in registers
+// tiles per diagonal wave; tiles per other wave, in registers and (past CREG,
+// from 273 bands on) in LDS, sized to the tile count T
 constexpr int cdiag_for(int T) { return (T + CDW - 1) / CDW; }
 constexpr int coff_for(int T) { return (T * (T - 1) / 2 + CNW - CDW - 1) / (CNW - CDW); }
+constexpr int creg_for(int T) { return coff_for(T) < CREG ? coff_for(T) : CREG; }
+constexpr int clds_for(int T) { return coff_for(T) - creg_for(T); }
 // lfac layout per block (doubles): Y_k at 256 k, L_ik at 256 (T + i (i - 1) / 2 + k), then
 // the equilibration scale [Bp].  Lane l of a stored tile holds, at 4 l + q, the element
 // (row l % 16, column l / 16 + 4 q): the A operand of four v_mfma_f64_16x16x4f64.
@@ -421,6 +81,7 @@ __device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\
 struct CholCtx {
   f64x4* lcol;           // [CMAXT][64] the pivot column F(L_ik), lane-major
   f64x4* ybuf;           // [2][64] F(Y_k), by step parity
+  f64x4* ltile;          // [NL][64] this wave's tiles kept in LDS (from 273 bands on)
   double* t22;           // [FTS] this wave's diagonal staging
   const double* sc;      // [Bp] equilibration scale
   int* flag;             // non-positive pivot seen
@@ -486,6 +147,23 @@ __device__ __forceinline__ void chol_diag(const CholCtx& c, f64x4* yout, double*
   if (lane == 0 && bad) *c.flag = 1;
 }
 
+// F(R_ij) of the equilibrated, regularised covariance: element (lr, lg + 4 r);
+// branch-free (every lane loads a valid address), padding selected away.
+__device__ __forceinline__ f64x4 load_tile(const CholCtx& c, int ti, int tj) {
+  const int lr = c.lane & 15, lg = c.lane >> 4;
+  f64x4 t;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * ti + lr, col = 16 * tj + lg + 4 * r;
+    const bool in = (row < c.B) && (col < c.B);
+    const int hi = in ? (row >= col ? row : col) : 0, lo = in ? (row >= col ? col : row) : 0;
+    double v = c.R[(int64_t)hi * c.Bp + lo] * c.rden + ((row == col) ? c.lam : 0.0);
+    v *= c.sc[row] * c.sc[col];
+    t[r] = in ? v : ((row == col) ? 1.0 : 0.0);
+  }
+  return t;
+}
+
 // The sweep of one wave over its NS tiles.  DIAG: the wave owns diagonal
 // tiles (k = wv + CDW s) and factors them; otherwise tiles below the
 // diagonal (index u = s (CNW - CDW) + wv - CDW in row-major order).  Every
@@ -495,7 +173,7 @@ __device__ __forceinline__ void chol_diag(const CholCtx& c, f64x4* yout, double*
 //   U: every tile with i >= j > k takes R_ij -= L_ik L_jk^T; the owner of
 //      (k+1, k+1) updates that tile first and factors it (the next step
 //      needs only Y_{k+1}), then its remaining tiles.
-template <int NS, bool DIAG>
+template <int NS, int NL, bool DIAG>
 __device__ __forceinline__ void chol_sweep(const CholCtx& c) {
   const int lane = c.lane, wv = c.wv, T = c.T, B = c.B, Bp = c.Bp;
   const int lr = lane & 15, lg = lane >> 4;
@@ -518,19 +196,23 @@ __device__ __forceinline__ void chol_sweep(const CholCtx& c) {
     ti[s] = __builtin_amdgcn_readfirstlane(i);
     tj[s] = __builtin_amdgcn_readfirstlane(j);
     tl[s] = f64x4{0.0, 0.0, 0.0, 0.0};
-    if (ti[s] >= 0) {
+    if (ti[s] >= 0) tl[s] = load_tile(c, ti[s], tj[s]);
+  }
+  // tiles past the register slots (from 273 bands on) live in LDS, each
+  // read and written only by its owner wave
+  int li[NL > 0 ? NL : 1], lj[NL > 0 ? NL : 1];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // F(R_ij): element (lr, lg + 4 r); branch-free, padding selected away
-        const int row = 16 * ti[s] + lr, col = 16 * tj[s] + lg + 4 * r;
-        const bool in = (row < B) && (col < B);
-        const int hi = in ? (row >= col ? row : col) : 0, lo = in ? (row >= col ? col : row) : 0;
-        double v = c.R[(int64_t)hi * Bp + lo] * c.rden + ((row == col) ? c.lam : 0.0);
-        v *= c.sc[row] * c.sc[col];
-        v = in ? v : ((row == col) ? 1.0 : 0.0);
-        tl[s][r] = v;
-      }
+  for (int s = 0; s < NL; ++s) {
+    int i = -1, j = -1;
+    const int u = (NS + s) * (CNW - CDW) + (wv - CDW);
+    if (u < T * (T - 1) / 2) {
+      i = 1;
+      while ((i + 1) * i / 2 <= u) ++i;
+      j = u - i * (i - 1) / 2;
     }
+    li[s] = __builtin_amdgcn_readfirstlane(i);
+    lj[s] = __builtin_amdgcn_readfirstlane(j);
+    if (li[s] >= 0) c.ltile[s * 64 + lane] = load_tile(c, li[s], lj[s]);
   }
 #pragma clang loop unroll(disable)
   for (int k = -1; k < T && !*c.flag; ++k) {
@@ -547,6 +229,17 @@ __device__ __forceinline__ void chol_sweep(const CholCtx& c) {
           *reinterpret_cast<f64x4*>(c.lf + lf_L(T, ti[s], k) + 4 * lane) = acc;
         }
       }
+#pragma unroll
+      for (int s = 0; s < NL; ++s) {
+        if (lj[s] == k && li[s] > k) {
+          const f64x4 t = c.ltile[s * 64 + lane];
+          f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(yk[q], t[q], acc, 0, 0, 0);
+          c.lcol[li[s] * 64 + lane] = acc;
+          *reinterpret_cast<f64x4*>(c.lf + lf_L(T, li[s], k) + 4 * lane) = acc;
+        }
+      }
     }
     if (k >= 0) lds_sync();
     const bool dw = DIAG && k + 1 < T && wv == (k + 1) % CDW;
@@ -555,9 +248,9 @@ __device__ __forceinline__ void chol_sweep(const CholCtx& c) {
       for (int s = 0; s < NS; ++s) {
         if (ti[s] == k + 1) {
           if (k >= 0) {
-            const f64x4 li = c.lcol[ti[s] * 64 + lane];
+            const f64x4 lk = c.lcol[ti[s] * 64 + lane];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-li[q], li[q], tl[s], 0, 0, 0);
+            for (int q = 0; q < 4; ++q) tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-lk[q], lk[q], tl[s], 0, 0, 0);
           }
           double* p = c.t22 + lr * 17 + lg;       // F(R) -> row-major
 #pragma unroll
@@ -572,10 +265,21 @@ __device__ __forceinline__ void chol_sweep(const CholCtx& c) {
       for (int s = 0; s < NS; ++s) {
         if (ti[s] > k && tj[s] > k && !(dw && ti[s] == k + 1)) {
           // element loads, so only the operands of one chunk need registers
-          const double* li = reinterpret_cast<const double*>(c.lcol + ti[s] * 64 + lane);
-          const double* lj = reinterpret_cast<const double*>(c.lcol + tj[s] * 64 + lane);
+          const double* pi = reinterpret_cast<const double*>(c.lcol + ti[s] * 64 + lane);
+          const double* pj = reinterpret_cast<const double*>(c.lcol + tj[s] * 64 + lane);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-lj[q], li[q], tl[s], 0, 0, 0);
+          for (int q = 0; q < 4; ++q) tl[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj[q], pi[q], tl[s], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NL; ++s) {
+        if (li[s] > k && lj[s] > k) {
+          const double* pi = reinterpret_cast<const double*>(c.lcol + li[s] * 64 + lane);
+          const double* pj = reinterpret_cast<const double*>(c.lcol + lj[s] * 64 + lane);
+          f64x4 t = c.ltile[s * 64 + lane];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) t = __builtin_amdgcn_mfma_f64_16x16x4f64(-pj[q], pi[q], t, 0, 0, 0);
+          c.ltile[s * 64 + lane] = t;
         }
       }
     }
@@ -583,7 +287,8 @@ __device__ __forceinline__ void chol_sweep(const CholCtx& c) {
   }
 }
 
-// One 1024-thread workgroup per block slot: conditioning as in k_factor,
+// One 1024-thread workgroup per block slot: conditioning (trace, ridge,
+// equilibration; a window too small or a non-positive variance stops here),
 // then the Cholesky sweep; the diagonal inverses and L tiles are handed over
 // to k_trinv, the status is set (0: factored, 1: singular, 2: not ready).
 template <int T_MAX>
@@ -596,9 +301,10 @@ __global__ void __launch_bounds__(CNT) k_chol(LaunchSet ls) {
   const int64_t bp2 = (int64_t)Bp * Bp;
   const double* R = d.m2_snap + b * bp2;
   double* lf = d.lfac + b * d.lf_stride;
-  __shared__ f64x4 lcol[CMAXT * 64];
+  __shared__ f64x4 lcol[T_MAX * 64];
   __shared__ f64x4 ybuf[2 * 64];
-  __shared__ double sc[16 * CMAXT];
+  __shared__ f64x4 ltile[(clds_for(T_MAX) > 0 ? clds_for(T_MAX) * (CNW - CDW) : 1) * 64];
+  __shared__ double sc[16 * T_MAX];
   __shared__ double t22[CDW][FTS];
   __shared__ double red[CNW];
   __shared__ int flag;
@@ -644,10 +350,11 @@ __global__ void __launch_bounds__(CNT) k_chol(LaunchSet ls) {
   }
   CholCtx c;
   c.lcol = lcol; c.ybuf = ybuf; c.t22 = t22[wv < CDW ? wv : 0]; c.sc = sc; c.flag = &flag;
+  c.ltile = ltile + (wv >= CDW ? (wv - CDW) * clds_for(T_MAX) * 64 : 0);
   c.R = R; c.lf = lf; c.rden = 1.0 / den; c.lam = lam;
   c.B = B; c.Bp = Bp; c.T = T; c.wv = wv; c.lane = lane;
-  if (wv < CDW) chol_sweep<cdiag_for(T_MAX), true>(c);
-  else chol_sweep<coff_for(T_MAX), false>(c);
+  if (wv < CDW) chol_sweep<cdiag_for(T_MAX), 0, true>(c);
+  else chol_sweep<creg_for(T_MAX), clds_for(T_MAX), false>(c);
   if (flag) {
     if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
     return;
@@ -849,24 +556,14 @@ extern "C" hipError_t rxk_launch_copy_slot(const rxk::LaunchSet* ls, int nb, hip
   return hipGetLastError();
 }
 
-template <int WP>
-static void launch_factor_t(const rxk::LaunchSet* ls, int wg, hipStream_t st) {
-  using namespace rxk;
-  int T = 0;                                // the largest band-tile count of the launch sizes the tile array
-  for (int i = 0; i < ls->nb; ++i) T = T > ls->d[i].Bp / 16 ? T : ls->d[i].Bp / 16;
-  if (T <= 12) hipLaunchKernelGGL((k_factor<WP, ftpw_for(12)>), dim3(wg), dim3(FNT), 0, st, *ls);
-  else if (T <= 17) hipLaunchKernelGGL((k_factor<WP, ftpw_for(17)>), dim3(wg), dim3(FNT), 0, st, *ls);
-  else if (T <= 19) hipLaunchKernelGGL((k_factor<WP, ftpw_for(19)>), dim3(wg), dim3(FNT), 0, st, *ls);
-  else hipLaunchKernelGGL((k_factor<WP, ftpw_for(MAXT)>), dim3(wg), dim3(FNT), 0, st, *ls);
-}
-
-// Up to 17 tiles (272 bands): k_chol, then k_trinv and (except on the FP64
-// path) k_wop, each with T workgroups per block.
+// k_chol (sized to the launch's largest tile count), then k_trinv and
+// (except on the FP64 path) k_wop, each with T workgroups per block.
 template <int WP>
 static hipError_t launch_factor3(const rxk::LaunchSet* ls, int wg, int T, hipStream_t st) {
   using namespace rxk;
   if (T <= 8) hipLaunchKernelGGL((k_chol<8>), dim3(wg), dim3(CNT), 0, st, *ls);
   else if (T <= 12) hipLaunchKernelGGL((k_chol<12>), dim3(wg), dim3(CNT), 0, st, *ls);
+  else if (T <= 17) hipLaunchKernelGGL((k_chol<17>), dim3(wg), dim3(CNT), 0, st, *ls);
   else hipLaunchKernelGGL((k_chol<CMAXT>), dim3(wg), dim3(CNT), 0, st, *ls);
   LaunchSet c = *ls;                        // T workgroups per block slot
   c.wg0[0] = 0;
@@ -883,23 +580,13 @@ extern "C" hipError_t rxk_launch_factor(int wprec, const rxk::LaunchSet* ls, int
   if (wg <= 0) return hipSuccess;
   int T = 0;
   for (int i = 0; i < ls->nb; ++i) T = T > ls->d[i].Bp / 16 ? T : ls->d[i].Bp / 16;
-  if (T <= CMAXT) {
-    switch (wprec) {
-      case P_F64: return launch_factor3<P_F64>(ls, wg, T, st);
-      case P_F32: return launch_factor3<P_F32>(ls, wg, T, st);
-      case P_BF16: return launch_factor3<P_BF16>(ls, wg, T, st);
-      case P_F16: return launch_factor3<P_F16>(ls, wg, T, st);
-      case P_FP8: return launch_factor3<P_FP8>(ls, wg, T, st);
-      default: return hipErrorInvalidValue;
-    }
-  }
+  if (T > CMAXT) return hipErrorInvalidValue;
   switch (wprec) {
-    case P_F64: launch_factor_t<P_F64>(ls, wg, st); break;
-    case P_F32: launch_factor_t<P_F32>(ls, wg, st); break;
-    case P_BF16: launch_factor_t<P_BF16>(ls, wg, st); break;
-    case P_F16: launch_factor_t<P_F16>(ls, wg, st); break;
-    case P_FP8: launch_factor_t<P_FP8>(ls, wg, st); break;
+    case P_F64: return launch_factor3<P_F64>(ls, wg, T, st);
+    case P_F32: return launch_factor3<P_F32>(ls, wg, T, st);
+    case P_BF16: return launch_factor3<P_BF16>(ls, wg, T, st);
+    case P_F16: return launch_factor3<P_F16>(ls, wg, T, st);
+    case P_FP8: return launch_factor3<P_FP8>(ls, wg, T, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }

@@ -2,15 +2,15 @@
 
 The three factor kernels (Cholesky sweep, column-tile inverse, operand rows)
 hand tiles over through a per-block buffer and write W and the whitening
-operand.  This walks the same index formulas for every band count the
-three-kernel path takes (1..272 bands, T <= 17 tiles) and for the tail of
-the single-workgroup kernel kept for 273..320 bands, and asserts that every
-access lies inside its buffer and that every tile is owned exactly once.
-The formulas are restated from the kernels; a change to one must be made
-here too."""
+operand.  This walks the same index formulas for every band count (1..320
+bands, T <= 20 tiles) and asserts that every access lies inside its buffer,
+that every tile is owned exactly once (in registers or, from 273 bands on,
+in LDS), and that the Cholesky workgroup's LDS fits a CU.  The formulas are
+restated from the kernels; a change to one must be made here too."""
 import pytest
 
-CNW, CDW, CMAXT, MAXT = 16, 3, 17, 20
+CNW, CDW, CMAXT, MAXT, CREG = 16, 3, 20, 20, 11
+LDS_BYTES = 160 * 1024
 
 
 def pad16(b):
@@ -23,6 +23,19 @@ def lf_tiles(T):
 
 def lf_stride(Bp):
     return 256 * lf_tiles(Bp // 16) + Bp
+
+
+def tmax_for(T):
+    return 8 if T <= 8 else (12 if T <= 12 else (17 if T <= 17 else 20))
+
+
+def chol_lds_bytes(t_max):
+    coff = -(-(t_max * (t_max - 1) // 2) // (CNW - CDW))
+    clds = coff - min(coff, CREG)
+    fts = 16 * 17
+    # lcol, ybuf, overflow tiles, sc, diagonal staging, red, flag
+    return (t_max * 64 * 32 + 2 * 64 * 32 + max(1, clds * (CNW - CDW)) * 64 * 32 + 16 * t_max * 8
+            + CDW * fts * 8 + CNW * 8 + 4)
 
 
 def chol_owners(T, t_max):
@@ -47,12 +60,17 @@ def chol_owners(T, t_max):
     return owned
 
 
+@pytest.mark.parametrize("t_max", [8, 12, 17, 20])
+def test_cholesky_workgroup_lds_fits(t_max):
+    assert chol_lds_bytes(t_max) <= LDS_BYTES
+
+
 @pytest.mark.parametrize("B", range(1, 16 * CMAXT + 1))
 def test_three_kernel_factor_indices_in_bounds(B):
     Bp = pad16(B)
     T = Bp // 16
     Bw = 32 * -(-Bp // 32)
-    t_max = 8 if T <= 8 else (12 if T <= 12 else CMAXT)
+    t_max = tmax_for(T)
     owned = chol_owners(T, t_max)
     assert sorted(owned) == sorted((i, j) for i in range(T) for j in range(i + 1))
     assert all(len(v) == 1 for v in owned.values())
@@ -94,24 +112,3 @@ def test_three_kernel_factor_indices_in_bounds(B):
                             assert i * Bw + jj < Bp * Bw and i * Bp + jj < Bp * Bp
                         if jj <= i and jj < B:
                             assert i * Bp + jj < Bp * Bp
-
-
-@pytest.mark.parametrize("B", range(16 * CMAXT + 1, 16 * MAXT + 1))
-def test_single_workgroup_factor_tail_in_bounds(B):
-    # the 273..320-band kernel: rows i0 = 4 wv + 32 n (< Bp), four rows each;
-    # columns j = lane + 64 c (c < 5); maxima read W[i Bp + j] for j <= i, j < B;
-    # the operand writes wl[i Bw + j] for j < 16 (i / 16 + 1)
-    Bp = pad16(B)
-    Bw = 32 * -(-Bp // 32)
-    for wv in range(8):
-        for i0 in range(4 * wv, Bp, 32):
-            for q in range(4):
-                i = i0 + q
-                assert i < Bp
-                for c in range(5):
-                    for lane in range(64):
-                        j = lane + 64 * c
-                        if j <= i and j < B:
-                            assert i * Bp + j < Bp * Bp
-                        if j < 16 * (i // 16 + 1):
-                            assert j < Bp and i * Bw + j < Bp * Bw and i * Bp + j < Bp * Bp
