@@ -12,7 +12,7 @@
 //   k_syrk   -- C = sum_p (x_p - c)(x_p - c)^T on matrix cores, lower 64x64
 //               super-tiles x split-K over pixel chunks, FP32 (or FP64)
 //               partials; diagonal super-tiles also emit exact raw band sums.
-//   k_merge_vec / k_merge_mat -- fixed-order FP64 reduction of the
+//   k_merge_vec / k_merge_red / k_merge_rec -- fixed-order FP64 reduction of the
 //               partials, exact shift correction M2_b = C - n e e^T
 //               (e = m_b - c), then the pairwise (Chan-Golub-LeVeque) update
 //               of the window (N, S1, M2), snapshotting it after every block.
@@ -783,47 +783,80 @@ __global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
 // Matrix part, by row strips: a workgroup owns 4 consecutive rows and 64
 // consecutive columns at or below the diagonal; wave w takes row 4g + w and
 // lane l column 64c + l, so every load of a split partial is one contiguous
-// 256-byte row segment.  Each wave runs all blocks for its 64 entries:
-// C_b = fixed-order FP64 sum of the split partials, M2_b = C_b - n_b e e^T
-// (exact shift correction), then the pairwise update M2 <- M2 + M2_b +
-// w d d^T (M2 <- M2_b for an empty window; M2 unchanged for a block with no
-// finite pixel), snapshotting the window's scatter matrix after every block.
-// (Fewer, fuller workgroups than one per tile quarter: they leave more of the
-// GPU to the whitening running beside them.)
+// 256-byte row segment.  Two launches, so the per-block sums over the split
+// partials (the bulk of the reads) run in parallel over blocks instead of
+// inside the recurrence over blocks:
+//   k_merge_red: one workgroup per (block, row strip): C_b = fixed-order FP64
+//     sum of the block's split partials, M2_b = C_b - n_b e e^T, written over
+//     the block's snapshot slot;
+//   k_merge_rec: one workgroup per row strip: the pairwise recurrence over
+//     the blocks in order (M <- M + M2_b + w d d^T; M <- M2_b for an empty
+//     window; M unchanged for a block with no finite pixel), each block's
+//     M2_b read back from its slot (loads independent of the recurrence,
+//     eight blocks ahead) and replaced by the window's scatter matrix after
+//     the block.
+__device__ __forceinline__ bool strip_entry(const BatchDesc& d, int q, int& gi, int& gj) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int g = 0;
+  while (q >= (4 * g + 67) / 64) { q -= (4 * g + 67) / 64; ++g; }
+  gi = 4 * g + w;
+  gj = 64 * q + lane;
+  return gi < d.B && gj <= gi;
+}
+
 template <typename PT>
-__global__ void __launch_bounds__(MB * MW) k_merge_mat(LaunchSet ls) {
+__global__ void __launch_bounds__(MB * MW) k_merge_red(LaunchSet ls) {
+  int local;
+  const int bi = find_batch(ls, blockIdx.x, local);
+  const BatchDesc& d = ls.d[bi];
+  int strips = 0;
+  for (int g = 0; g < d.Bp / 4; ++g) strips += (4 * g + 67) / 64;
+  const int b = local / strips, q = local % strips;
+  int gi, gj;
+  if (!strip_entry(d, q, gi, gj)) return;
+  const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
+  const double nb = d.nbv[b];
+  const int ksb = ks_of(d, b);
+  const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
+  double c = 0.0;
+  int sp = 0;
+  for (; sp + 4 <= ksb; sp += 4) {             // four loads in flight, summed in order
+    const double a0 = (double)pb[sp * bp2], a1 = (double)pb[(sp + 1) * bp2];
+    const double a2 = (double)pb[(sp + 2) * bp2], a3 = (double)pb[(sp + 3) * bp2];
+    c += a0;
+    c += a1;
+    c += a2;
+    c += a3;
+  }
+  for (; sp < ksb; ++sp) c += (double)pb[sp * bp2];
+  const int64_t o = (int64_t)b * d.Bp;
+  d.m2_snap[b * bp2 + e] = c - nb * d.ev[o + gi] * d.ev[o + gj];
+}
+
+__global__ void __launch_bounds__(MB * MW) k_merge_rec(LaunchSet ls) {
   int q;
   const int bi = find_batch(ls, blockIdx.x, q);
   const BatchDesc& d = ls.d[bi];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int g = 0;                                       // row group: columns 0 .. 4g + 3 in 64-wide chunks
-  while (q >= (4 * g + 67) / 64) { q -= (4 * g + 67) / 64; ++g; }
-  const int gi = 4 * g + w, gj = 64 * q + lane;
-  if (!(gi < d.B && gj <= gi)) return;
+  int gi, gj;
+  if (!strip_entry(d, q, gi, gj)) return;
   const int64_t bp2 = (int64_t)d.Bp * d.Bp, e = (int64_t)gi * d.Bp + gj;
   double m2 = d.m2_in[e];
   if (d.causal == 1) d.m2_snap[d.nblk * bp2 + e] = (d.reset_bits & 1ull) ? 0.0 : m2;   // window before the batch
-  for (int b = 0; b < d.nblk; ++b) {
-    const double nb = d.nbv[b];
-    const int ksb = ks_of(d, b);
-    const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
-    double c = 0.0;
-    int sp = 0;
-    for (; sp + 4 <= ksb; sp += 4) {             // four loads in flight, summed in order
-      const double a0 = (double)pb[sp * bp2], a1 = (double)pb[(sp + 1) * bp2];
-      const double a2 = (double)pb[(sp + 2) * bp2], a3 = (double)pb[(sp + 3) * bp2];
-      c += a0;
-      c += a1;
-      c += a2;
-      c += a3;
+  constexpr int PF = 8;                            // blocks whose M2_b are loaded ahead
+  for (int b0 = 0; b0 < d.nblk; b0 += PF) {
+    double mbv[PF];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) mbv[t] = (b0 + t < d.nblk) ? d.m2_snap[(b0 + t) * bp2 + e] : 0.0;
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int b = b0 + t;
+      if (b >= d.nblk) break;
+      const int64_t o = (int64_t)b * d.Bp;
+      if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
+      const double wgt = d.coef[b];
+      if (wgt >= 0.0) m2 = (wgt > 0.0) ? m2 + mbv[t] + wgt * d.dv[o + gi] * d.dv[o + gj] : mbv[t];
+      d.m2_snap[b * bp2 + e] = m2;
     }
-    for (; sp < ksb; ++sp) c += (double)pb[sp * bp2];
-    const int64_t o = (int64_t)b * d.Bp;
-    const double mb = c - nb * d.ev[o + gi] * d.ev[o + gj];
-    if ((d.reset_bits >> b) & 1ull) m2 = 0.0;
-    const double wgt = d.coef[b];
-    if (wgt >= 0.0) m2 = (wgt > 0.0) ? m2 + mb + wgt * d.dv[o + gi] * d.dv[o + gj] : mb;
-    d.m2_snap[b * bp2 + e] = m2;
   }
   d.m2_out[e] = m2;
 }
@@ -847,8 +880,12 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const r
   if (phase == 2) {
     if (wg > 0) hipLaunchKernelGGL(k_merge_vec, dim3(wg), dim3(MB * MW), 0, st, *ls);
     if (wg2 > 0) {
-      if (prec == P_F64) hipLaunchKernelGGL((k_merge_mat<double>), dim3(wg2), dim3(MB * MW), 0, st, *ls2);
-      else hipLaunchKernelGGL((k_merge_mat<float>), dim3(wg2), dim3(MB * MW), 0, st, *ls2);
+      LaunchSet r = *ls2;                     // the strips of every block of each batch
+      r.wg0[0] = 0;
+      for (int i = 0; i < r.nb; ++i) r.wg0[i + 1] = r.wg0[i] + (ls2->wg0[i + 1] - ls2->wg0[i]) * r.d[i].nblk;
+      if (prec == P_F64) hipLaunchKernelGGL((k_merge_red<double>), dim3(r.wg0[r.nb]), dim3(MB * MW), 0, st, r);
+      else hipLaunchKernelGGL((k_merge_red<float>), dim3(r.wg0[r.nb]), dim3(MB * MW), 0, st, r);
+      hipLaunchKernelGGL(k_merge_rec, dim3(wg2), dim3(MB * MW), 0, st, *ls2);
     }
     return hipGetLastError();
   }
