@@ -16,6 +16,7 @@
 //               partials, exact shift correction M2_b = C - n e e^T
 //               (e = m_b - c), then the pairwise (Chan-Golub-LeVeque) update
 //               of the window (N, S1, M2), snapshotting it after every block.
+#include <atomic>
 #include <type_traits>
 
 #include "rx_dev.h"
@@ -471,8 +472,15 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <int P>
+// R > 1 (launches with few splits, e.g. a lone block): R workgroups share a
+// split, all staging every chunk of it; workgroup r of the R multiplies only
+// the fragment columns j = r (mod R) of each super-tile.  Every output
+// fragment sees the same MFMA sequence (chunk order, then the two 32-sample
+// steps) as with R = 1, so the partials are bit-identical whatever R is.
+template <int P, int R>
 __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
+  static_assert(R == 1 || R == 2 || R == 4, "fragment columns per super-tile split evenly");
+  constexpr int NJ = 4 / R;                      // fragment columns per wave
   using M = MM<P>;
   using S = typename M::storage;
   static_assert(M::KV == 8 && sizeof(S) == 2, "16-bit operand formats only");
@@ -486,6 +494,8 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   int local;
   const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
+  const int cgrp = local % R;                    // this workgroup's fragment columns
+  local /= R;
   int b = local / d.ks, split = local % d.ks;
   if (b >= d.nblk - 1) { b = d.nblk - 1; split = local - (d.nblk - 1) * d.ks; }
   const int ksb = ks_of(d, b);
@@ -583,11 +593,11 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   }
   const int nsup = (nBp + 63) >> 6;
   const bool active = I < nsup;
-  typename M::acc acc[4][4];
+  typename M::acc acc[4][NJ];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = typename M::acc{};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = typename M::acc{};
   const int lr = lane & 15, lkg = lane >> 4;
 
   auto multiply = [&](const uint16_t* tb) {
@@ -596,15 +606,16 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
     for (int st = 0; st < KC / 32; ++st) {
       const int g = 4 * st + lkg;               // 8-value k-group within the chunk
       const int off = lr * KC + 8 * (g ^ (lr & 7));
-      typename M::frag a[4], bq[4];
+      typename M::frag a[4], bq[NJ];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bq[j] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * J + 16 * j) * KC + off));
+      for (int j = 0; j < NJ; ++j)
+        bq[j] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * J + 16 * (cgrp + R * j)) * KC + off));
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) a[ii] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * I + 16 * ii) * KC + off));
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[ii][j] = M::mma(a[ii], bq[j], acc[ii][j]);
+        for (int j = 0; j < NJ; ++j) acc[ii][j] = M::mma(a[ii], bq[j], acc[ii][j]);
     }
   };
   // Each lane converts exactly the 16 bytes it loaded itself (same row and
@@ -687,8 +698,8 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int ti = 4 * I + ii, tj = 4 * J + j;
+      for (int j = 0; j < NJ; ++j) {
+        const int ti = 4 * I + ii, tj = 4 * J + cgrp + R * j;
         if (16 * ti < d.Bp && ti >= tj) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -698,6 +709,7 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
         }
       }
   }
+  if (cgrp != 0) return;                         // one workgroup of the R writes the band sums
 #pragma unroll
   for (int q = 0; q < S2IT; ++q) {
     double t = (double)rawsum[q];
@@ -861,6 +873,21 @@ __global__ void __launch_bounds__(MB * MW) k_merge_rec(LaunchSet ls) {
   d.m2_out[e] = m2;
 }
 
+// Workgroups per split of the direct-load covariance kernel: the largest of
+// 4, 2, 1 that keeps the launch within the device's CU count (one workgroup
+// per CU).  The choice only spreads work; it never changes a partial.
+static int syrk3_share(int wg) {
+  static std::atomic<int> cus[64];
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1;
+  n = cus[dev].load(std::memory_order_relaxed);
+  if (n == 0) {
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 1;
+    cus[dev].store(n, std::memory_order_relaxed);
+  }
+  return (4 * wg <= n) ? 4 : ((2 * wg <= n) ? 2 : 1);
+}
+
 }  // namespace rxk
 
 // Host entry used by the runtime: phase 3 validity (float input, before
@@ -916,8 +943,20 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const r
       ++t.nb;
     }
     if (a.nb > 0) {
-      if (prec == P_BF16) hipLaunchKernelGGL((k_syrk3<P_BF16>), dim3(a.wg0[a.nb]), dim3(S2NT), 0, st, a);
-      else hipLaunchKernelGGL((k_syrk3<P_F16>), dim3(a.wg0[a.nb]), dim3(S2NT), 0, st, a);
+      // few splits in the launch (a lone block has about 11): share each
+      // split among R workgroups so the launch still covers most CUs
+      const int R = syrk3_share(a.wg0[a.nb]);
+      for (int i = 0; i <= a.nb; ++i) a.wg0[i] *= R;
+      const dim3 g(a.wg0[a.nb]);
+      if (prec == P_BF16) {
+        if (R == 4) hipLaunchKernelGGL((k_syrk3<P_BF16, 4>), g, dim3(S2NT), 0, st, a);
+        else if (R == 2) hipLaunchKernelGGL((k_syrk3<P_BF16, 2>), g, dim3(S2NT), 0, st, a);
+        else hipLaunchKernelGGL((k_syrk3<P_BF16, 1>), g, dim3(S2NT), 0, st, a);
+      } else {
+        if (R == 4) hipLaunchKernelGGL((k_syrk3<P_F16, 4>), g, dim3(S2NT), 0, st, a);
+        else if (R == 2) hipLaunchKernelGGL((k_syrk3<P_F16, 2>), g, dim3(S2NT), 0, st, a);
+        else hipLaunchKernelGGL((k_syrk3<P_F16, 1>), g, dim3(S2NT), 0, st, a);
+      }
     }
     if (o.nb > 0) {
       if (prec == P_BF16) hipLaunchKernelGGL((k_syrk2<IN_U16, P_BF16>), dim3(o.wg0[o.nb]), dim3(S2NT), 0, st, o);

@@ -386,6 +386,39 @@ def test_push_pattern_and_queue_mode_do_not_change_scores(rxm):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_covariance_split_sharing_does_not_change_scores(rxm, fmt):
+    # Launches with few covariance splits share each split among 2 or 4
+    # workgroups (fragment columns dealt out among them); a launch with many
+    # keeps one per split.  50-line blocks of 640 samples have 6 splits: the
+    # 24-block push takes one workgroup per split, pushes of 1 to 6 blocks
+    # four, the 11-block push two.  Scores must match bit for bit.
+    B, S, BL = 150, 640, 50
+    cube = synth.sensor_cube(43, lines=24 * BL, samples=S, bands=B).cube
+    x = dev(cube)
+    assert rxm.split_plan(rxm.make_config(B, S, in_dtype=np.uint16, syrk=fmt, whiten=fmt, block_lines=BL),
+                          BL)[0] == 6
+
+    def cfg():
+        return rxm.make_config(B, S, in_dtype=np.uint16, syrk=fmt, whiten=fmt, ridge_rel=1e-6, block_lines=BL)
+    ref = rxm.RxStream(cfg())
+    ref.rx_push_lines(x)
+    ref.rx_sync()
+    want = ref.scores_host()
+    ref.rx_destroy()
+    st = rxm.RxStream(cfg())
+    l0 = 0
+    for nb in (1, 1, 5, 11, 6):
+        st.rx_push_lines(x[l0:l0 + nb * BL])
+        l0 += nb * BL
+        st.rx_sync()
+    got = st.scores_host()
+    st.rx_destroy()
+    assert l0 == cube.shape[0]
+    assert np.all(np.isfinite(want))
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
 def test_relative_mask_maximum_over_pending_after_partial_pops(rxm):
     # The relative mask's maximum is over exactly the pending scores: after a
     # partial pop, after a push on top of a partly popped set, and after a
