@@ -11,6 +11,8 @@
 // with power-of-two scales: input band scale 2^-e_k (e_k = floor(log2
 // sigma_k)) and output row scale 2^f_i chosen so each row fits the format's
 // range.
+#include <type_traits>
+
 #include "rx_dev.h"
 
 namespace rxk {
@@ -96,8 +98,23 @@ struct CholCtx {
 // S[i][4cg..4cg+3] and the eliminated identity E[i][4cg..4cg+3].  Column j:
 // pivot p = S[j][j], 1/sqrt(p) from the hardware estimate and two Newton
 // steps, L[i][j] = S[i][j]/sqrt(p), Y[j][.] = E[j][.]/sqrt(p), then
-// S[i][k] -= L[i][j] L[k][j] (j < k <= i) and E[i][.] -= L[i][j] Y[j][.]
-// (i > j).  Y = L^{-1} goes, as F(Y), to yout (LDS) and yg (hand-off).
+// S[i][k] -= L[i][j] L[k][j] (i, k > j) and E[i][.] -= L[i][j] Y[j][.]
+// (i > j).  S is kept whole and symmetric (it starts from the lower
+// triangle, and both halves take the same products), so L[k][j] = S[j][k] /
+// sqrt(p) and Y[j][.] sit in the lane's own 16-lane row, at position j: a
+// row broadcast (DPP row_newbcast) fetches them; only L[i][j], held in row
+// group j / 4, crosses rows.  Y = L^{-1} goes, as F(Y), to yout (LDS) and yg
+// (hand-off).
+template <int N> __device__ __forceinline__ double row_bcast(double x) {
+  const int2 v = __builtin_bit_cast(int2, x);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(0, v.x, 0x150 + N, 0xF, 0xF, false);   // row_newbcast:N
+  r.y = __builtin_amdgcn_update_dpp(0, v.y, 0x150 + N, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+
+template <int J> using icj = std::integral_constant<int, J>;
+
 __device__ __forceinline__ void chol_diag(const CholCtx& c, f64x4* yout, double* yg) {
   const int lane = c.lane;
   int i = lane & 15, cg = lane >> 4;
@@ -105,13 +122,13 @@ __device__ __forceinline__ void chol_diag(const CholCtx& c, f64x4* yout, double*
   double v[4], y[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    v[e] = c.t22[i * 17 + 4 * cg + e];
-    y[e] = (i == 4 * cg + e) ? 1.0 : 0.0;
+    const int col = 4 * cg + e;
+    v[e] = c.t22[(i >= col ? i * 17 + col : col * 17 + i)];
+    y[e] = (i == col) ? 1.0 : 0.0;
   }
   bool bad = false;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const int je = j & 3, jg = j >> 2;
+  auto column = [&](auto J) {
+    constexpr int j = decltype(J)::value, je = j & 3, jg = j >> 2;
     const double piv = readlane_d(v[je], j + 16 * jg);
     bad |= !(piv > 0.0);
     double rd = __builtin_amdgcn_rsq(piv);
@@ -124,17 +141,21 @@ __device__ __forceinline__ void chol_diag(const CholCtx& c, f64x4* yout, double*
     double lkj[4], yj[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      lkj[e] = __shfl(v[je], (4 * cg + e) + 16 * jg, 64) * rd;
-      yj[e] = __shfl(y[e], j + 16 * cg, 64) * rd;
+      lkj[e] = row_bcast<j>(v[e]) * rd;
+      yj[e] = row_bcast<j>(y[e]) * rd;
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int kk = 4 * cg + e;
-      if (kk > j && i >= kk) v[e] -= lij * lkj[e];
+      if (kk > j && i > j) v[e] -= lij * lkj[e];
       y[e] = (i == j) ? yj[e] : ((i > j) ? y[e] - lij * yj[e] : y[e]);
     }
     __builtin_amdgcn_sched_barrier(0);
-  }
+  };
+  column(icj<0>{});  column(icj<1>{});  column(icj<2>{});  column(icj<3>{});
+  column(icj<4>{});  column(icj<5>{});  column(icj<6>{});  column(icj<7>{});
+  column(icj<8>{});  column(icj<9>{});  column(icj<10>{}); column(icj<11>{});
+  column(icj<12>{}); column(icj<13>{}); column(icj<14>{}); column(icj<15>{});
   // Y row-major into the staging tile, then read back as F(Y)
   double* ys = c.t22;
 #pragma unroll
