@@ -26,13 +26,12 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# An unserved stream runs on three HIP streams (covariance, merge + factor,
-# whitening) and the cube is pushed from a fourth.  HIP maps streams onto a
-# small pool of hardware queues (4 by default); two of these sharing one
-# queue serialise the pipeline, so the process asks for at least 8 (set
-# before the runtime starts).
-if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 8 and not os.environ.get("RX_BENCH_KEEP_QUEUES"):
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+# An unserved stream runs on three HIP streams (covariance and merge,
+# factorisation, whitening) beside torch's; the cube is resident and pushed
+# as RX_LINES_RESIDENT (no fourth stream), so HIP's default pool of 4
+# hardware queues per process holds the pipeline.  The queue count is left
+# as the environment sets it and reported.
+HW_QUEUES = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
 
 LINES, SAMPLES, BANDS, BLOCK = 2000, 640, 270, 100
 RIDGE = 1e-6
@@ -146,14 +145,16 @@ def run_path(rx, torch, x, prec, steps, warmup, label, repeats=0):
     npx = LINES * SAMPLES
     sc = torch.empty(npx, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
     mk = torch.empty((npx + 7) // 8, dtype=torch.uint8, device="cuda")
-    # the resident cube is pushed from its own stream (it is ready and never
-    # changes), so a push does not wait behind the previous push's mask and
-    # score pops on torch's stream: one push's factorisation and whitening
-    # overlap the next push's covariance product
-    s_in = torch.cuda.Stream()
+    # the cube is resident (written and synchronised before the timed
+    # steps, never changed): RX_LINES_RESIDENT pushes order themselves
+    # against no caller stream, so a push does not wait behind the previous
+    # push's mask and score pops on torch's stream, one push's factorisation
+    # and whitening overlap the next push's covariance product, and the
+    # process needs only the library's three queues beside torch's
+    torch.cuda.synchronize()
 
     def step():
-        st.rx_push_lines(x, stream=s_in, guard=False)
+        st.rx_push_lines(x, resident=True)
         st.rx_mask(0.110, rx.RX_THR_REL_MAX, 0, mk)
         st.rx_scores(sc)
 
@@ -331,12 +332,12 @@ def one_block_pushes(rx, torch, x, prec, steps=10, warmup=2):
                          window_lines=LINES)
     st = rx.RxStream(cfg)
     sc = torch.empty(BLOCK * SAMPLES, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
-    s_in = torch.cuda.Stream()
     blocks = [x[b * BLOCK:(b + 1) * BLOCK] for b in range(LINES // BLOCK)]
+    torch.cuda.synchronize()
 
     def cube():
         for blk in blocks:
-            st.rx_push_lines(blk, stream=s_in, guard=False)
+            st.rx_push_lines(blk, resident=True)      # lines already in HBM
             st.rx_scores(sc)
 
     for _ in range(warmup):
@@ -470,22 +471,6 @@ def precision_report(rx, torch, x, cube, sc_bf16, sc_fp32, ref_bf16):
         out[w] = row
     del x4
     return out
-
-
-def headline_at_default_queues(steps):
-    """The headline step in a child process left at HIP's default of 4
-    hardware queues per process (this process asks for 8): the mixed-path
-    rate a library user with defaults gets."""
-    import subprocess
-    env = dict(os.environ)
-    env["GPU_MAX_HW_QUEUES"] = "4"
-    env["RX_BENCH_KEEP_QUEUES"] = "1"
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--headline-only", "--steps", str(steps)],
-                       env=env, capture_output=True, text=True, timeout=300)
-    if r.returncode != 0:
-        return {"error": r.stderr[-400:]}
-    rec = json.loads(r.stdout.strip().splitlines()[-1])
-    return {"hw_queues": 4, "value": rec["value"], "ms_per_step": rec["ms_per_step"]}
 
 
 def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.0):
@@ -638,7 +623,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="arrival window of the served-streams run (0 skips it)")
@@ -646,8 +631,6 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="profiler runs: the mixed-path steps, the one-block pushes and the block latency "
                          "only (then the reference copy, if asked); prints no JSON line")
-    ap.add_argument("--headline-only", action="store_true",
-                    help="time the mixed-path step only and print its JSON line (used for the 4-queue figure)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="end with one device-to-device copy of this many MiB: the reference kernel that "
                          "scales hardware byte counters under rocprofv3")
@@ -668,10 +651,7 @@ def main():
     npx = LINES * SAMPLES
 
     t_mix, ms_mix, n_mix, sc_mix, spread = run_path(rx, torch, x, "bf16", args.steps, args.warmup, "mixed bf16",
-                                                     repeats=0 if args.headline_only else 10)
-    if args.headline_only:
-        print(json.dumps({"value": npx / t_mix, "ms_per_step": t_mix * 1e3, "steps": args.steps}), flush=True)
-        return
+                                                     repeats=10)
     if args.profile:
         obp = one_block_pushes(rx, torch, x, "bf16", steps=3, warmup=1)
         p50, p99 = latency(rx, torch, x, "bf16", 20)
@@ -764,8 +744,6 @@ def main():
     if "bf16" in prec_rep:
         for k, v in prec_rep["bf16"]["mask_agreement"].items():
             log(f"mask {k}: {v['decided_mismatches']} decided mismatches, {v['in_band']} inside the band")
-    q4 = headline_at_default_queues(args.steps)
-    log(f"headline at 4 hardware queues: {q4}")
 
     # roofline of the dominant kernel of the mixed path: the phase with the
     # largest share of the step's CU-time (launch time, timed live with HIP
@@ -812,13 +790,13 @@ def main():
         "dtype": "bf16", "data": "synthetic (seeded mixed-endmember 12-bit sensor cube)",
         "config": {"workload": "sensor cube 2000 lines x 640 samples x 270 bands uint16, 20 blocks of 100 "
                                "lines, update-then-score, BF16 covariance + whitening, FP64 factor, ridge 1e-6",
-                   "lines": LINES, "samples": SAMPLES, "bands": BANDS, "block_lines": BLOCK},
+                   "lines": LINES, "samples": SAMPLES, "bands": BANDS, "block_lines": BLOCK,
+                   "hw_queues": HW_QUEUES},
         "fp64_path": None if args.skip_fp64 else {"value": npx / t_64, "ms_per_step": t_64 * 1e3, "steps": k64,
                                                   "roofline": fp64_roof},
         "mixed_over_fp64": None if args.skip_fp64 else t_64 / t_mix,
         "fp32_path": None if args.skip_fp64 else {"value": npx / t_32, "ms_per_step": t_32 * 1e3, "steps": k64},
         "value_repeats": spread,
-        "value_at_4_hw_queues": q4,
         "one_block_pushes": obp,
         "latency_ms": {"block_lines": BLOCK, "p50": p50, "p99": p99, "samples": 200},
         "latency_ms_causal": {"block_lines": BLOCK, "p50": c50, "p99": c99, "samples": 200},

@@ -69,6 +69,10 @@ typedef enum { RX_IN_U16 = 0, RX_IN_F32 = 1, RX_IN_F64 = 2 } rx_in_type;
  * device; the scores are bit for bit those of the same lines pushed as BIL).  Served streams
  * take BIL blocks only. */
 typedef enum { RX_BIL = 0, RX_BIP = 1 } rx_layout;
+
+/* Where rx_push_lines' lines are (its is_device_ptr argument). */
+enum { RX_LINES_HOST = 0, RX_LINES_DEVICE = 1, RX_LINES_RESIDENT = 2 };
+
 typedef enum { RX_FP64 = 0, RX_FP32 = 1, RX_BF16 = 2, RX_FP16 = 3, RX_FP8_E4M3 = 4 } rx_prec;
 typedef enum { RX_THR_ABS = 0, RX_THR_REL_MAX = 1, RX_THR_TOPK = 2 } rx_thr_mode;
 
@@ -145,10 +149,16 @@ rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
 
 /* Push n_lines >= 1 lines, BIL [n_lines][B][S] (or BIP [n_lines][S][B] with
  * cfg->layout = RX_BIP) of cfg->in_type, contiguous.
- * is_device_ptr = 0: lines is host memory, copied before the call returns
- * (the caller may reuse it at once).  is_device_ptr = 1: lines is device
- * memory on cfg->device; it is read asynchronously and must stay unchanged
- * until rx_sync returns or hip_stream passes an rx_wait on this stream.
+ * is_device_ptr = RX_LINES_HOST (0): lines is host memory, copied before the
+ * call returns (the caller may reuse it at once).  RX_LINES_DEVICE (1):
+ * lines is device memory on cfg->device, read asynchronously after the work
+ * already queued on hip_stream; it must stay unchanged until rx_sync returns
+ * or hip_stream passes an rx_wait on this stream.  RX_LINES_RESIDENT (2):
+ * device memory whose contents are complete when the call is made (written
+ * by work the caller has already synchronised with); the push orders itself
+ * against no stream (hip_stream is ignored), which leaves the caller's
+ * streams out of the stream's queues; the same lifetime rule as
+ * RX_LINES_DEVICE.  Any other value: RX_E_ARG.
  * The lines are cut into blocks (cfg->block_lines, window edges); each block
  * updates the statistics and is then scored.  Scores join the stream's
  * pending FIFO in pixel order (p = line * S + sample).  Asynchronous.

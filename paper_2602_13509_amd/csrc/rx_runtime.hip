@@ -896,6 +896,7 @@ struct Pipe {
   hipEvent_t* ev_white;    // [2]
   int par;
   bool causal_copy;        // a causal stream whose next batch copies this batch's last slot
+  bool in_event = true;    // a lone stream's input is ordered by its ev_in (not for resident lines)
 };
 static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, rx_stream* prof = nullptr) {
   const bool piped = qs.A != qs.C;
@@ -965,7 +966,7 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, 
   // not wait behind the host time of the statistics launches)
   const bool early = ps && jobs[0].fast;
   if (early) {
-    HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
+    if (pe->in_event) HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
     rx_status r0 = whiten_all();
     if (r0 != RX_OK) return r0;
   }
@@ -1063,6 +1064,9 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
   if (s->srv) return fail(RX_E_STATE, "served streams take blocks through rx_server_submit");
   if (!lines) return fail(RX_E_ARG, "null lines");
   if (n_lines < 1) return fail(RX_E_ARG, "n_lines must be >= 1");
+  if (is_device_ptr < RX_LINES_HOST || is_device_ptr > RX_LINES_RESIDENT)
+    return fail(RX_E_ARG, "is_device_ptr must be RX_LINES_HOST, RX_LINES_DEVICE or RX_LINES_RESIDENT");
+  const bool resident = is_device_ptr == RX_LINES_RESIDENT;
   HIPC(hipSetDevice(s->dev));
   const size_t bytes = (size_t)n_lines * s->B * s->S * s->esz;
   const void* x = lines;
@@ -1092,7 +1096,7 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
   if (!one_queue && s->st_only_tail) HIPC(hipStreamWaitEvent(s->stA, s->ev_last, 0));
   if (!is_device_ptr) {
     if ((r = stage_host_input(s, lines, bytes, &x)) != RX_OK) return r;
-  } else {
+  } else if (!resident) {
     HIPC(hipEventRecord(s->ev_in, static_cast<hipStream_t>(hip_stream)));
     HIPC(hipStreamWaitEvent(qs.A, s->ev_in, 0));     // queues B and C follow A by events
   }
@@ -1110,7 +1114,8 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready, true)) != RX_OK) { s->broken = true; return r; }
     // (float input: the whitening also reads the validity pass's output)
     jobs[0].fast = jobs[0].copy && k - i == 1 && is_device_ptr && !one_queue && s->in_type == RX_IN_U16;
-    const Pipe pe{s->ev_merged, s->ev_fact, s->ev_white, jobs[0].par, s->causal != 0};
+    // resident lines need no input event (a BIP push's copy on queue A does)
+    const Pipe pe{s->ev_merged, s->ev_fact, s->ev_white, jobs[0].par, s->causal != 0, !resident || bip};
     if ((r = launch_jobs(jobs, qs, &pe, s)) != RX_OK) { s->broken = true; return r; }
   }
   if (!is_device_ptr) HIPC(hipEventRecord(s->ev_stage, s->st));   // last reader of the staging buffer

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "librx.so")
 RX_OK, RX_E_ARG, RX_E_NOMEM, RX_E_NOTREADY, RX_E_SINGULAR, RX_E_DEVICE, RX_E_BUDGET, RX_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 RX_IN_U16, RX_IN_F32, RX_IN_F64 = 0, 1, 2
 RX_BIL, RX_BIP = 0, 1
+RX_LINES_HOST, RX_LINES_DEVICE, RX_LINES_RESIDENT = 0, 1, 2
 RX_FP64, RX_FP32, RX_BF16, RX_FP16, RX_FP8_E4M3 = 0, 1, 2, 3, 4
 RX_THR_ABS, RX_THR_REL_MAX, RX_THR_TOPK = 0, 1, 2
 RX_FLAG_CAUSAL = 1
@@ -178,7 +179,7 @@ class RxStream:
         self.score_f64 = cfg.whiten_prec == RX_FP64
 
     # -- core path
-    def rx_push_lines(self, lines, stream=None, allow_notready=True, guard=True) -> int:
+    def rx_push_lines(self, lines, stream=None, allow_notready=True, guard=True, resident=False) -> int:
         """lines: BIL [n_lines][B][S] (BIP [n_lines][S][B] for an RX_BIP stream)
         torch tensor (device or host) or numpy array.
 
@@ -190,13 +191,21 @@ class RxStream:
         cannot overwrite the lines before they are read.  guard=False leaves
         the caller's stream free (so one push's tail can overlap the next
         push): the tensor must then stay alive and unchanged until rx_sync or
-        an rx_wait, as the C interface states."""
+        an rx_wait, as the C interface states.
+        resident=True (device tensors already written, e.g. after a
+        synchronisation): RX_LINES_RESIDENT, the push orders itself against
+        no stream and stream / guard are not used; the tensor must stay alive
+        and unchanged until rx_sync."""
         n = lines.shape[0]
         shape = (self.S, self.B) if self.cfg.layout == RX_BIP else (self.B, self.S)
         assert tuple(lines.shape[1:]) == shape, lines.shape
         dev = _is_dev(lines)
+        if resident:
+            assert dev, "resident lines are device memory"
+            return check(LIB.rx_push_lines(self.h, _ptr(lines), n, RX_LINES_RESIDENT, 0),
+                         allow=(RX_E_NOTREADY,) if allow_notready else ())
         sh = _stream_handle(stream) if dev else 0
-        r = check(LIB.rx_push_lines(self.h, _ptr(lines), n, dev, sh),
+        r = check(LIB.rx_push_lines(self.h, _ptr(lines), n, RX_LINES_DEVICE if dev else RX_LINES_HOST, sh),
                   allow=(RX_E_NOTREADY,) if allow_notready else ())
         if dev and guard:
             check(LIB.rx_wait(self.h, sh))

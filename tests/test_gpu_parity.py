@@ -419,6 +419,37 @@ def test_covariance_split_sharing_does_not_change_scores(rxm, fmt):
     assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
+def test_resident_pushes_equal_device_pushes(rxm):
+    # RX_LINES_RESIDENT orders a push against no caller stream; the lines are
+    # the same, so are the scores, bit for bit, for one-block and multi-block
+    # pushes, update-then-score and causal.  Other values are refused and the
+    # stream stays usable.
+    import torch
+    B, S, BL = 96, 256, 16
+    cube = synth.sensor_cube(47, lines=6 * BL, samples=S, bands=B).cube
+    x = dev(cube)
+    torch.cuda.synchronize()
+    for causal in (False, True):
+        def cfg():
+            return rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                                   block_lines=BL, causal=causal)
+        a, b = rxm.RxStream(cfg()), rxm.RxStream(cfg())
+        for l0, nb in ((0, 1), (BL, 3), (4 * BL, 1), (5 * BL, 1)):
+            a.rx_push_lines(x[l0:l0 + nb * BL])
+            b.rx_push_lines(x[l0:l0 + nb * BL], resident=True)
+        a.rx_sync()
+        b.rx_sync()
+        sa, sb = a.scores_host(), b.scores_host()
+        assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))
+        assert np.isfinite(sa[-BL * S:]).all()
+        a.rx_destroy()
+        r = rxm.LIB.rx_push_lines(b.h, x.data_ptr(), BL, 3, None)
+        assert r == rxm.RX_E_ARG, r
+        b.rx_push_lines(x[:BL], resident=True)
+        b.rx_sync()
+        b.rx_destroy()
+
+
 def test_relative_mask_maximum_over_pending_after_partial_pops(rxm):
     # The relative mask's maximum is over exactly the pending scores: after a
     # partial pop, after a push on top of a partly popped set, and after a
