@@ -191,6 +191,8 @@ __global__ void __launch_bounds__(NT) k_syrk(LaunchSet ls) {
         T v[8];
         if (bvalid && d.vec_ok && k0 + 8 <= nvalid) {
           load8(row + k0, v);
+        } else if (IN == IN_U16 && bvalid && d.vec8_ok && k0 + 8 <= nvalid) {
+          load8_a8(row + k0, v);
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = (bvalid && k0 + j < nvalid) ? row[k0 + j] : T(0);
@@ -318,6 +320,10 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
         if (d.vec_ok && k0 + 8 <= nvalid) {
 #pragma unroll
           for (int w = 0; w < RW; ++w) raw[q][w] = reinterpret_cast<const uint4*>(row + k0)[w];
+        } else if (IN == IN_U16 && d.vec8_ok && k0 + 8 <= nvalid) {
+          const uint2 h0 = reinterpret_cast<const uint2*>(row + k0)[0];
+          const uint2 h1 = reinterpret_cast<const uint2*>(row + k0)[1];
+          raw[q][0] = uint4{h0.x, h0.y, h1.x, h1.y};
         } else {
           T t[8];
 #pragma unroll
@@ -747,8 +753,19 @@ __global__ void __launch_bounds__(MB * MW) k_merge_vec(LaunchSet ls) {
   for (int b = w; b < d.nblk; b += MW) {
     const int ksb = ks_of(d, b);
     double t = 0.0;
-    if (in)
-      for (int s = 0; s < ksb; ++s) t += d.psum[((int64_t)b * d.ks + s) * d.Bp + k];
+    if (in) {
+      // eight loads in flight, added in split order
+      const double* ps = d.psum + (int64_t)b * d.ks * d.Bp + k;
+      int s = 0;
+      for (; s + 8 <= ksb; s += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = ps[(int64_t)(s + u) * d.Bp];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t += a[u];
+      }
+      for (; s < ksb; ++s) t += ps[(int64_t)s * d.Bp];
+    }
     sb[b][lane] = t;
     shb[b][lane] = (k < d.Bp) ? d.shift[(int64_t)b * d.Bp + k] : 0.0;
   }
@@ -832,13 +849,12 @@ __global__ void __launch_bounds__(MB * MW) k_merge_red(LaunchSet ls) {
   const PT* pb = static_cast<const PT*>(d.part) + (int64_t)b * d.ks * bp2 + e;
   double c = 0.0;
   int sp = 0;
-  for (; sp + 4 <= ksb; sp += 4) {             // four loads in flight, summed in order
-    const double a0 = (double)pb[sp * bp2], a1 = (double)pb[(sp + 1) * bp2];
-    const double a2 = (double)pb[(sp + 2) * bp2], a3 = (double)pb[(sp + 3) * bp2];
-    c += a0;
-    c += a1;
-    c += a2;
-    c += a3;
+  for (; sp + 8 <= ksb; sp += 8) {             // eight loads in flight, summed in order
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = (double)pb[(sp + u) * bp2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c += a[u];
   }
   for (; sp < ksb; ++sp) c += (double)pb[sp * bp2];
   const int64_t o = (int64_t)b * d.Bp;

@@ -71,6 +71,8 @@ __global__ void __launch_bounds__(NT) k_whiten(LaunchSet ls, int Bw) {
         T v[8];
         if (d.vec_ok && k0 + 8 <= nvalid) {
           load8(row + k0, v);
+        } else if (IN == IN_U16 && d.vec8_ok && k0 + 8 <= nvalid) {
+          load8_a8(row + k0, v);
         } else {
 #pragma unroll
           for (int j = 0; j < 8; ++j) v[j] = (k0 + j < nvalid) ? row[k0 + j] : T(0);
@@ -266,7 +268,9 @@ __host__ __device__ constexpr int w2_groups(int p, int ns) {
 
 // ls.wg0 holds the prefix of tiles per batch (not workgroups).  NS is the
 // number of 32-band steps, ceil(nT / 2), the same for every batch of the
-// launch.  Requires S % 8 == 0 and 16-byte aligned rows (vec_ok).
+// launch.  Requires S % 4 == 0 and 8-byte aligned rows (vec8_ok); the last
+// tile of a line may reach past its end (those samples are read from the
+// line's start and their scores are not stored).
 template <int P, int NS, int G>
 __global__ void __launch_bounds__(W2NT) k_whiten2(LaunchSet ls, int Bw, int64_t ntile_all) {
   using M = MM<P>;
@@ -709,9 +713,10 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
   if (wg <= 0) return hipSuccess;
   if (in_type == IN_U16 && (wprec == P_BF16 || wprec == P_F16 || wprec == P_FP8) && Bw % 32 == 0 && Bw >= 32 &&
       Bw <= 32 * MAXS) {
-    // batches of 16-bit rows with S % 8 == 0 and 16-byte aligned starts
-    // (vec_ok) take the tile kernel, the others the chunk kernel; the choice
-    // is per batch (both give the same scores, bit for bit)
+    // batches of 16-bit rows with S % 4 == 0 and 8-byte aligned starts
+    // (vec8_ok: a lane's G <= 4 samples are one aligned load) take the tile
+    // kernel, the others the chunk kernel; the choice is per batch (both
+    // give the same scores, bit for bit)
     const int ns = Bw / 32;                                  // the launch shares Bw = 32 ceil(nT / 2)
     const int G = w2_groups(wprec, ns);
     LaunchSet t, o;
@@ -721,7 +726,7 @@ extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const rxk::Launc
       const BatchDesc& d = ls->d[i];
       const int64_t tpl = (d.S + 16 * G - 1) / (16 * G);
       const int64_t tiles = ((int64_t)(d.nblk - 1) * d.blk_lines + d.last_lines) * tpl;
-      if (d.vec_ok && d.S % 8 == 0 && (int64_t)t.wg0[t.nb] + tiles <= INT32_MAX) {
+      if (d.vec8_ok && (int64_t)t.wg0[t.nb] + tiles <= INT32_MAX) {
         t.d[t.nb] = d;
         t.wg0[t.nb + 1] = t.wg0[t.nb] + (int)tiles;
         ++t.nb;

@@ -157,6 +157,14 @@ __device__ __forceinline__ void load8(const uint16_t* p, uint16_t v[8]) {
   v[0] = q.x & 0xffff; v[1] = q.x >> 16; v[2] = q.y & 0xffff; v[3] = q.y >> 16;
   v[4] = q.z & 0xffff; v[5] = q.z >> 16; v[6] = q.w & 0xffff; v[7] = q.w >> 16;
 }
+// The same from an 8-byte aligned address (two 8-byte loads): 16-bit rows
+// with S % 4 == 0, such as the imager's 900-sample lines.
+__device__ __forceinline__ void load8_a8(const uint16_t* p, uint16_t v[8]) {
+  const uint2 a = reinterpret_cast<const uint2*>(p)[0], b = reinterpret_cast<const uint2*>(p)[1];
+  v[0] = a.x & 0xffff; v[1] = a.x >> 16; v[2] = a.y & 0xffff; v[3] = a.y >> 16;
+  v[4] = b.x & 0xffff; v[5] = b.x >> 16; v[6] = b.y & 0xffff; v[7] = b.y >> 16;
+}
+template <typename T> __device__ __forceinline__ void load8_a8(const T*, T*) {}
 __device__ __forceinline__ void load8(const float* p, float v[8]) {
   const float4 a = *reinterpret_cast<const float4*>(p);
   const float4 b = *reinterpret_cast<const float4*>(p + 4);
@@ -250,6 +258,7 @@ struct BatchDesc {
   int ks, ks_last;        // covariance split count per block / for the last block
   int nsr, nsup;          // super-rows ceil(Bp/64); lower super-tiles nsr(nsr+1)/2
   int vec_ok;             // 16-byte vector loads of input rows are aligned
+  int vec8_ok;            // 16-bit input: 8-byte loads of rows are aligned (S % 4 == 0)
   int nrect;              // covariance rectangles (16-tile units) owned by the waves of one workgroup
   uint8_t rect[16][4];    // per wave: first tile row, first tile column, tile rows, tile columns
   int ddof;

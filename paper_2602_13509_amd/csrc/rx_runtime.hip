@@ -154,13 +154,14 @@ static bool whole_triangle(int sp) { return sp == RX_BF16 || sp == RX_FP16 || sp
 // The covariance kernels keep each split's raw band sums of 16-bit input as
 // exact uint32 per thread, and a thread adds 8 values of at most 65535 per
 // chunk: a split of at most kMaxChunksPerSplit chunks cannot wrap
-// (8 * 65535 * 8192 = 4 294 901 760 < 2^32).  Splits are capped at 64 per
-// block unless a block is so long that 64 would exceed that.
+// (8 * 65535 * 8192 = 4 294 901 760 < 2^32).  Splits are capped at
+// kMaxSplits per block unless a block is so long that this would exceed that.
 static constexpr int64_t kMaxChunksPerSplit = 8192;
+static constexpr int kMaxSplits = 256;              // splits per block (about one per CU)
 static int splits_for(int64_t lines, int cpl, int sp) {
   const int per = whole_triangle(sp) ? kSplitChunks2 : kSplitChunks;
   const int64_t nch = lines * cpl;
-  const int64_t cap = std::max<int64_t>(64, (nch + kMaxChunksPerSplit - 1) / kMaxChunksPerSplit);
+  const int64_t cap = std::max<int64_t>(kMaxSplits, (nch + kMaxChunksPerSplit - 1) / kMaxChunksPerSplit);
   return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (nch + per - 1) / per));
 }
 
@@ -745,6 +746,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   d.nsr = ceil_div(s->Bp, SUP);
   d.nsup = d.nsr * (d.nsr + 1) / 2;
   d.vec_ok = ((reinterpret_cast<uintptr_t>(d.x) & 15) == 0) && (((size_t)s->S * s->esz) % 16 == 0);
+  d.vec8_ok = s->in_type == RX_IN_U16 && ((reinterpret_cast<uintptr_t>(d.x) & 7) == 0) && (s->S % 4 == 0);
   d.ddof = s->cfg.ddof;
   d.rho = s->cfg.ridge_rel;
   uint64_t rb = 0;

@@ -330,16 +330,18 @@ def test_determinism_bitwise(rxm):
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
-@pytest.mark.parametrize("fmt,B", [("bf16", 270), ("fp16", 270), ("fp8", 270), ("fp8", 180)])
-def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt, B):
-    # 16-bit rows with 16-byte aligned starts take the 32-pixel tile kernel;
-    # the same lines pushed from a buffer offset by one element take the
-    # chunk kernel.  Both centre, scale and round identically and run the same
-    # matrix-core chains, so with FP64 statistics (computed identically on
-    # both routes) the scores must match bit for bit.  S = 200 leaves a
-    # ragged last tile; 3 blocks put block boundaries inside workgroup ranges.
+@pytest.mark.parametrize("fmt,B,S", [("bf16", 270, 200), ("fp16", 270, 200), ("fp8", 270, 200), ("fp8", 180, 200),
+                                     ("bf16", 70, 100), ("bf16", 270, 100), ("fp8", 180, 100)])
+def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt, B, S):
+    # 16-bit rows with 8-byte aligned starts and S % 4 == 0 take the
+    # 64-pixel tile kernel; the same lines pushed from a buffer offset by one
+    # element take the chunk kernel.  Both centre, scale and round identically
+    # and run the same matrix-core chains, so with FP64 statistics (computed
+    # identically on both routes) the scores must match bit for bit.  S = 200
+    # and S = 100 (S % 8 = 4, 8-byte rows like the imager's 900 samples)
+    # leave a ragged last tile; 3 blocks put block boundaries inside
+    # workgroup ranges.
     import torch
-    S = 200
     cube = synth.sensor_cube(26, lines=90, samples=S, bands=B).cube
     say(f"tile vs chunk whitening {fmt}: 90x{S}x{B} u16, blocks of 40")
     a = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten=fmt, block_lines=40))
@@ -350,6 +352,35 @@ def test_tile_whitening_equals_chunk_whitening_bitwise(rxm, fmt, B):
     assert off.data_ptr() % 16 == 2
     b = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="fp64", whiten=fmt, block_lines=40))
     b.rx_push_lines(off.view(cube.shape))   # same bits; the library reads them as uint16
+    a.rx_sync()
+    b.rx_sync()
+    sa, sb = a.scores_host(), b.scores_host()
+    assert np.all(np.isfinite(sa))
+    assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))
+
+
+@pytest.mark.parametrize("syrk", ["bf16", "fp16", "fp32"])
+def test_eight_byte_rows_equal_element_loads_bitwise(rxm, syrk):
+    # 900-sample-like rows (S % 8 = 4): from an 8-byte aligned buffer the
+    # register-staged covariance kernels and the tile whitening load 8 bytes
+    # at a time; from a buffer offset by one element they load element by
+    # element (and the whitening takes the chunk kernel).  Same values, same
+    # arithmetic: the scores match bit for bit, one push and several.
+    import torch
+    B, S, BL = 70, 100, 30
+    cube = synth.sensor_cube(48, lines=4 * BL, samples=S, bands=B).cube
+    flat = torch.empty(cube.size + 1, dtype=torch.int16, device="cuda")
+    flat[1:].copy_(dev(cube.view(np.int16).reshape(-1)))
+    off = flat[1:].view(cube.shape)
+    assert off.data_ptr() % 8 == 2
+    x = dev(cube)
+    cfg = dict(in_dtype=np.uint16, syrk=syrk, whiten="bf16", ridge_rel=1e-6, block_lines=BL)
+    a = rxm.RxStream(rxm.make_config(B, S, **cfg))
+    b = rxm.RxStream(rxm.make_config(B, S, **cfg))
+    a.rx_push_lines(x[:BL])
+    a.rx_push_lines(x[BL:])
+    b.rx_push_lines(off[:BL])
+    b.rx_push_lines(off[BL:])
     a.rx_sync()
     b.rx_sync()
     sa, sb = a.scores_host(), b.scores_host()

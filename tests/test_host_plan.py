@@ -18,7 +18,7 @@ U32 = 2 ** 32
 def test_split_plan_never_overflows_raw_sums(syrk, samples):
     cfg = rx.make_config(270, samples, syrk=syrk)
     cpl = -(-samples // 64)
-    for lines in (1, 7, 100, 128, 1000, 52428, 52429, 60000, 10 ** 6, 2 ** 31 - 1):
+    for lines in (1, 7, 100, 128, 1000, 52428, 52429, 60000, 209715, 209716, 10 ** 6, 2 ** 31 - 1):
         ks, mc = rx.split_plan(cfg, lines)
         nch = lines * cpl
         assert ks >= 1 and mc >= 1
@@ -30,17 +30,19 @@ def test_split_plan_never_overflows_raw_sums(syrk, samples):
 def test_split_plan_of_usual_blocks_is_unchanged():
     # 100-line blocks of 640 samples: 11 splits of at most 91 chunks (the
     # whole-triangle kernels), 16 of at most 64 (the super-tile kernels);
-    # up to 64 splits the plan is ceil(chunks / per-split) as before
+    # up to 256 splits (about one per CU) the plan is ceil(chunks / per-split)
     assert rx.split_plan(rx.make_config(270, 640, syrk="bf16"), 100) == (11, 91)
     assert rx.split_plan(rx.make_config(270, 640, syrk="fp64"), 100) == (16, 63)
-    for lines in (1, 16, 100, 500, 582):
+    for lines in (1, 16, 100, 500, 582, 1000, 2000, 2329, 5000):
         nch = lines * 10
-        assert rx.split_plan(rx.make_config(270, 640, syrk="bf16"), lines)[0] == min(64, -(-nch // 91))
-    # 52429 lines: 524 290 chunks, which 64 splits could only hold with 8193
-    # chunks in one (past the bound); the plan takes 65 splits instead
-    assert rx.split_plan(rx.make_config(270, 640, syrk="bf16"), 52428) == (64, 8192)
-    ks, mc = rx.split_plan(rx.make_config(270, 640, syrk="bf16"), 52429)
-    assert ks == 65 and mc <= 8192
+        assert rx.split_plan(rx.make_config(270, 640, syrk="bf16"), lines)[0] == min(256, -(-nch // 91))
+    # the paper's 1000-line cubes of 900 samples: 15 000 chunks, 165 splits
+    assert rx.split_plan(rx.make_config(70, 900, syrk="bf16"), 1000) == (165, 91)
+    # 209 716 lines: 2 097 160 chunks, which 256 splits could only hold with
+    # 8193 chunks in one (past the bound); the plan takes 257 splits instead
+    assert rx.split_plan(rx.make_config(270, 640, syrk="bf16"), 209715) == (256, 8192)
+    ks, mc = rx.split_plan(rx.make_config(270, 640, syrk="bf16"), 209716)
+    assert ks == 257 and mc <= 8192
 
 
 def test_split_plan_rejects_bad_arguments():
