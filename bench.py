@@ -504,7 +504,10 @@ def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.
     held = [[] for _ in specs]            # blocks of a stream not admitted yet: tags
     left = [len(sp.block_lines) for sp in specs]
     admitted_late = 0
-    ev = sorted((0.0 if replay_all_at_once else float(t) / compress, i, int(n))
+    # (release time, arrival time, stream, lines): all at once keeps the
+    # arrival order, so the streams' blocks are submitted interleaved as
+    # they arrived, not stream after stream
+    ev = sorted((0.0 if replay_all_at_once else float(t) / compress, float(t), i, int(n))
                 for i, sp in enumerate(specs) for t, n in zip(sp.arrivals, sp.block_lines))
     sub_ns, px_of, owner, lines_of = {}, {}, {}, {}
 
@@ -532,7 +535,7 @@ def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.
     while len(lat) < len(ev):
         now = time.perf_counter() - t0
         while k < len(ev) and ev[k][0] <= now:
-            _, i, n = ev[k]
+            _, _, i, n = ev[k]
             sub_ns[tag] = rx.clock_ns()           # arrival stamp; a held block's wait counts too
             t_first = sub_ns[tag] if t_first is None else t_first
             px_of[tag], owner[tag], lines_of[tag] = n * specs[i].samples, i, n
