@@ -588,9 +588,9 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
   };
 
   // wave wv owns the 64x64 super-tile (I, J), I >= J, of the lower triangle
-  // (at most 15 of them for 320 bands); it multiplies all 16 tiles of it and
-  // keeps the lower ones.  Rows past the band count read ring rows that are
-  // either zero or never written out.
+  // (at most 15 of them for 320 bands); it multiplies the fragment rows of it
+  // that hold a stored tile and keeps the lower tiles.  Rows past the band
+  // count read ring rows that are either zero or never written out.
   int I = 0, J = 0;
   {
     int t = wv;
@@ -605,6 +605,18 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) acc[i][j] = typename M::acc{};
   const int lr = lane & 15, lkg = lane >> 4;
+  // fragment rows that hold no stored fragment (past the padded band count,
+  // or wholly above the diagonal) are not multiplied; the stored fragments'
+  // MFMA sequences are unchanged
+  uint32_t rowm = 0;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int jc = cgrp + R * j;
+      if (64 * I + 16 * ii < nBp && 64 * J + 16 * jc < nBp && (I > J || ii >= jc)) rowm |= 1u << ii;
+    }
+  rowm = __builtin_amdgcn_readfirstlane(rowm);
 
   auto multiply = [&](const uint16_t* tb) {
     if (!active) return;
@@ -617,11 +629,12 @@ __global__ void __launch_bounds__(S2NT) k_syrk3(LaunchSet ls) {
       for (int j = 0; j < NJ; ++j)
         bq[j] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * J + 16 * (cgrp + R * j)) * KC + off));
 #pragma unroll
-      for (int ii = 0; ii < 4; ++ii) a[ii] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * I + 16 * ii) * KC + off));
-#pragma unroll
       for (int ii = 0; ii < 4; ++ii)
+        if ((rowm >> ii) & 1u) {
+          a[ii] = load_frag<P>(reinterpret_cast<const S*>(tb + (64 * I + 16 * ii) * KC + off));
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[ii][j] = M::mma(a[ii], bq[j], acc[ii][j]);
+          for (int j = 0; j < NJ; ++j) acc[ii][j] = M::mma(a[ii], bq[j], acc[ii][j]);
+        }
     }
   };
   // Each lane converts exactly the 16 bytes it loaded itself (same row and
