@@ -159,6 +159,37 @@ def test_band_counts(rxm, B):
     assert_scores(st2.scores_host(), ref, B, *TOL["fp32"], label=f"B={B} fp32")
 
 
+@pytest.mark.parametrize("B,S", [(16, 128), (100, 128), (200, 100), (272, 128), (288, 128), (289, 96),
+                                 (320, 128), (320, 100)])
+def test_band_counts_mixed_path(rxm, B, S):
+    # The BF16 path across the factor kernel's tile counts (T = 1 .. 20: the
+    # register-only sweep, the LDS overflow tiles from 273 bands, the largest
+    # 320), the whitening kernel's 32-band step counts and both row
+    # alignments (S % 8 == 0: 16-byte rows; S = 100, 8-byte rows), against
+    # the FP64 oracle with the same ridge.  The score is a sum of B squared
+    # whitened terms whose rounding errors are independent, so its relative
+    # error shrinks as 1/sqrt(B): below 270 bands the 270-band BF16 bounds
+    # are scaled by sqrt(270 / B).
+    cube = synth.sensor_cube(15, lines=24, samples=S, bands=B).cube
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=8, rho=1e-6)
+    st = run_stream(rxm, cube, "bf16", "bf16", ridge_rel=1e-6, block_lines=8)
+    f = max(1.0, (270.0 / B) ** 0.5)
+    assert_scores(st.scores_host(), ref, B, TOL["bf16"][0] * f, TOL["bf16"][1] * f, label=f"B={B} S={S} bf16")
+
+
+@pytest.mark.parametrize("S", [1, 3, 7, 65])
+def test_narrow_lines_mixed_path(rxm, S):
+    # Lines narrower than one 64-sample chunk or with a ragged chunk: the
+    # register-staged covariance and the chunk whitening (element loads),
+    # many lines per block.
+    B = 30
+    cube = synth.sensor_cube(16, lines=320, samples=S, bands=B).cube
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=64, rho=1e-6)
+    st = run_stream(rxm, cube, "bf16", "bf16", ridge_rel=1e-6, block_lines=64)
+    f = (270.0 / B) ** 0.5                       # as in test_band_counts_mixed_path
+    assert_scores(st.scores_host(), ref, B, TOL["bf16"][0] * f, TOL["bf16"][1] * f, label=f"S={S} bf16")
+
+
 # ---------------------------------------------------------------------------- statistics and factor hooks
 def test_stats_match_exact_integer_covariance(rxm):
     B, S = 270, 128
