@@ -20,6 +20,13 @@ counts the others), score NaN and are counted in `nonfinite`; a block is
 causal=True takes the other reading of the line-based detector: every block
 is scored with the window as it was before the block joined it (a block that
 starts a window has no statistics and is "notready").
+
+one_pass=True scores every block of a push with the window as it was before
+the push: with one block per push this is the causal reading above, and a
+push of several blocks is scored as one unit against the earlier lines (the
+statistics still update block by block).  A block whose window started
+inside the push, at or before it, has no earlier statistics and is
+"notready".
 """
 from __future__ import annotations
 
@@ -30,9 +37,11 @@ from . import rx
 
 class RxStreamOracle:
     def __init__(self, bands: int, samples: int, ddof: int = 0, rho: float = 0.0,
-                 window_lines: int = 0, block_lines: int = 0, causal: bool = False):
+                 window_lines: int = 0, block_lines: int = 0, causal: bool = False,
+                 one_pass: bool = False):
         self.B, self.S = bands, samples
         self.causal = causal
+        self.one_pass = one_pass
         self.ddof, self.rho = ddof, rho
         self.window_lines = window_lines
         self.block_lines = block_lines
@@ -79,14 +88,20 @@ class RxStreamOracle:
         assert lines.ndim == 3 and lines.shape[1] == self.B and lines.shape[2] == self.S
         out = []
         off = 0
+        # one_pass: the window before the push (None once a window has
+        # started inside the push)
+        before = self._state() if self.one_pass else None
         for pos, take in self._blocks(lines.shape[0]):
             if self.window_lines > 0 and pos % self.window_lines == 0:
                 self._reset()
+                before = None
             blk = lines[off:off + take]
             off += take
             px = rx.pixels(blk)
             is_int = np.issubdtype(px.dtype, np.integer)
-            if self.causal:
+            if self.one_pass:
+                out.append(self._score_with(before, px))  # the window before the push
+            elif self.causal:
                 out.append(self._score_block(px))         # the window before the block
             if self.is_int is None:
                 self.is_int = is_int
@@ -101,9 +116,25 @@ class RxStreamOracle:
                 self.n += int(ok.sum())
                 self.nonfinite += int((~ok).sum())
             self.lines_seen = pos + take
-            if not self.causal:
+            if not self.causal and not self.one_pass:
                 out.append(self._score_block(px))         # update, then score
         return np.concatenate(out) if out else np.zeros(0)
+
+    def _state(self):
+        """A copy of the window state (count, moments, kept float pixels)."""
+        return (self.n, self.s1.copy(), self.s2.copy(), list(self.float_px), self.is_int)
+
+    def _score_with(self, state, px):
+        """Scores of px with the window `state` (from _state); None: no window."""
+        if state is None:
+            self.status.append("notready")
+            return np.full(px.shape[0], np.nan)
+        now = self._state()
+        self.n, self.s1, self.s2, self.float_px, self.is_int = state
+        try:
+            return self._score_block(px)
+        finally:
+            self.n, self.s1, self.s2, self.float_px, self.is_int = now
 
     def _score_block(self, px):
         if (self.n <= self.B and self.rho == 0.0) or self.n <= self.ddof:

@@ -428,3 +428,59 @@ def test_causal_blocks_scored_with_the_window_before_them(window_lines):
             exact.append(float(sum(d[i] * inv[i][j] * d[j] for i in range(B) for j in range(B))))
         assert _rel(got[blk], exact) <= 1e-12
     assert o.status == want_status
+
+
+# ---------------------------------------------------------------- one-pass scoring
+@pytest.mark.parametrize("window_lines", [0, 6])
+def test_one_pass_blocks_scored_with_the_window_before_the_push(window_lines):
+    # Every block of a push is scored with exact-rational quadratic forms over
+    # the lines of the window that came before the push (Gauss-Jordan
+    # inverse); a block whose window started inside the push, at or before
+    # it, has no earlier statistics and is not ready.  Pushes of 3, 5 and 4
+    # lines in blocks of at most 2 lines.
+    L, B, S, bl = 12, 3, 5, 2
+    cube = np.random.default_rng(11).integers(0, 9, size=(L, B, S)).astype(np.uint16)
+    o = RxStreamOracle(B, S, block_lines=bl, window_lines=window_lines, one_pass=True)
+    pushes = [(0, 3), (3, 8), (8, 12)]
+    got = np.concatenate([o.push(cube[a:b]) for a, b in pushes])
+    px = rx.pixels(cube)
+    want_status = []
+    for a, b in pushes:
+        w0 = 0 if window_lines == 0 else (a // window_lines) * window_lines
+        prev = px[w0 * S:a * S]
+        l0 = a
+        while l0 < b:
+            take = min(bl, b - l0)
+            if window_lines:
+                take = min(take, window_lines - l0 % window_lines)
+            blk = slice(l0 * S, (l0 + take) * S)
+            reset_inside = window_lines and any(l % window_lines == 0 for l in range(a, l0 + 1))
+            if reset_inside or prev.shape[0] <= B:
+                want_status.append("notready")
+                assert np.isnan(got[blk]).all()
+            else:
+                want_status.append("ok")
+                mu, cov = brute.exact_stats(prev.tolist())
+                inv = brute.gauss_jordan_inverse(cov)
+                exact = []
+                for p in px[blk]:
+                    d = [int(p[j]) - mu[j] for j in range(B)]
+                    exact.append(float(sum(d[i] * inv[i][j] * d[j] for i in range(B) for j in range(B))))
+                assert _rel(got[blk], exact) <= 1e-12
+            l0 += take
+    assert o.status == want_status
+
+
+def test_one_pass_with_one_block_pushes_is_the_causal_reading():
+    # one block per push: the window before the push is the window before the
+    # block, so both modes give the same scores (the causal mode is pinned
+    # against exact rationals above)
+    L, B, S, bl = 10, 4, 7, 2
+    cube = np.random.default_rng(12).integers(0, 50, size=(L, B, S)).astype(np.uint16)
+    a = RxStreamOracle(B, S, block_lines=bl, window_lines=6, one_pass=True, rho=1e-3)
+    c = RxStreamOracle(B, S, block_lines=bl, window_lines=6, causal=True, rho=1e-3)
+    ga = np.concatenate([a.push(cube[i:i + bl]) for i in range(0, L, bl)])
+    gc = c.push(cube)
+    assert np.array_equal(np.isnan(ga), np.isnan(gc))
+    assert np.array_equal(ga[~np.isnan(ga)], gc[~np.isnan(gc)])
+    assert a.status == c.status
