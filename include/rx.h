@@ -99,7 +99,7 @@ typedef struct rx_config {
                              (blocks never straddle a window edge; 1000 = the paper's cube) */
   double ridge_rel;       /* rho >= 0: lambda = rho * trace(Sigma) / B is added to the diagonal */
   int32_t device;         /* HIP device ordinal */
-  int32_t flags;          /* RX_FLAG_CAUSAL or 0; other bits must be 0 */
+  int32_t flags;          /* 0, RX_FLAG_CAUSAL or RX_FLAG_ONE_PASS; other bits must be 0 */
 } rx_config;
 
 /* rx_config.flags: causal scoring.  Every block is scored with the window
@@ -114,6 +114,21 @@ typedef struct rx_config {
  * own statistics update (it runs alongside).  Default off: update, then
  * score. */
 #define RX_FLAG_CAUSAL 1
+
+/* rx_config.flags: one-pass scoring.  Every block of a push is scored with
+ * the window as it was before the push (with one block per push this is the
+ * causal reading above, the line-based detector of Section "Discussion /
+ * Performance"; the blocks of a longer push are scored together, as the
+ * paper scores a cube as one unit).  The statistics still take every block,
+ * and a block whose window started inside the push, at or before it, has no
+ * earlier statistics: NaN scores, not ready.  16-bit input with 16-byte
+ * aligned rows, S % 8 == 0, at most 272 bands and BF16 covariance and
+ * whitening products then reads every line once: one kernel stages each
+ * chunk of lines, whitens and scores it with the window before the push and
+ * adds it to the covariance product (Section "System Implementation /
+ * Detection Algorithm", Eq. 1).  Other configurations take the same scores
+ * from the two-pass kernels.  Not with RX_FLAG_CAUSAL. */
+#define RX_FLAG_ONE_PASS 2
 
 typedef struct rx_counters {
   int64_t lines_pushed;     /* lines accepted so far */
@@ -306,7 +321,8 @@ rx_status rx_set_stats(rx_stream* s, int64_t n, const double* mean, const double
 /* Phase timing for measurement: with enable = 1, every later push records a
  * pair of HIP events on the stream the kernels run on around each phase
  * (0 centring shift, 1 covariance product, 2 statistics merge, 3 FP64
- * factorisation, 4 whitening + score).  rx_phase_times blocks, then writes the
+ * factorisation, 4 whitening + score; a one-pass kernel, covariance product
+ * and scores together, counts as 1).  rx_phase_times blocks, then writes the
  * accumulated milliseconds ms[5] and launch counts launches[5] since the
  * last rx_profile call (which also resets them). */
 rx_status rx_profile(rx_stream* s, int32_t enable);

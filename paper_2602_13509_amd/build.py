@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librx.so")
-SOURCES = ["k_stats.hip", "k_factor.hip", "k_whiten.hip", "k_transmit.hip", "k_bin.hip", "rx_runtime.hip"]
+SOURCES = ["k_stats.hip", "k_factor.hip", "k_whiten.hip", "k_onepass.hip", "k_transmit.hip", "k_bin.hip", "rx_runtime.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -317,6 +317,7 @@ __global__ void __launch_bounds__(CNT) k_chol(LaunchSet ls) {
   int b;
   const int bi = find_batch(ls, blockIdx.x, b);
   const BatchDesc& d = ls.d[bi];
+  b += d.fslot0;
   const int B = d.B, Bp = d.Bp;
   const int T = Bp / 16;
   const int64_t bp2 = (int64_t)Bp * Bp;
@@ -334,14 +335,15 @@ __global__ void __launch_bounds__(CNT) k_chol(LaunchSet ls) {
   const double N = d.n_snap[b];
 
   if (tid == 0) d.clipflag[b] = 0;             // set by the whitening of this batch
-  // the block this slot scores (causal mode: slot b scores block b + 1, the
-  // extra slot nblk block 0, the last slot none in this batch); the stream's
-  // singular / not-ready counters count scored blocks
-  const int sbk = !d.causal ? b : (b == d.nblk ? 0 : (b + 1 < d.nblk ? b + 1 : -1));
-  const bool counted = sbk >= 0 && !causal_empty(d, sbk);
-  if (tid == 0 && sbk >= 0 && causal_empty(d, sbk)) atomicAdd(d.nsing + 1, 1u);
+  // the blocks this slot scores (causal mode: slot b scores block b + 1, the
+  // extra slot nblk block 0, the last slot none in this batch; one-pass
+  // mode: slot nblk scores every block); the stream's singular / not-ready
+  // counters count scored blocks
+  int counted, nostats;
+  slot_scores(d, b, counted, nostats);
+  if (tid == 0 && nostats > 0) atomicAdd(d.nsing + 1, (unsigned)nostats);
   if ((d.rho == 0.0 && N <= (double)B) || !(N - (double)d.ddof > 0.0)) {
-    if (tid == 0) { d.status[b] = 2; if (counted) atomicAdd(d.nsing + 1, 1u); }
+    if (tid == 0) { d.status[b] = 2; if (counted) atomicAdd(d.nsing + 1, (unsigned)counted); }
     return;
   }
   const double den = N - (double)d.ddof;
@@ -366,7 +368,7 @@ __global__ void __launch_bounds__(CNT) k_chol(LaunchSet ls) {
   }
   __syncthreads();
   if (flag) {
-    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
+    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, (unsigned)counted); }
     return;
   }
   CholCtx c;
@@ -377,7 +379,7 @@ __global__ void __launch_bounds__(CNT) k_chol(LaunchSet ls) {
   if (wv < CDW) chol_sweep<cdiag_for(T_MAX), 0, true>(c);
   else chol_sweep<creg_for(T_MAX), clds_for(T_MAX), false>(c);
   if (flag) {
-    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, 1u); }
+    if (tid == 0) { d.status[b] = 1; if (counted) atomicAdd(d.nsing, (unsigned)counted); }
     return;
   }
   if (tid == 0) d.status[b] = 0;
@@ -400,7 +402,7 @@ __global__ void __launch_bounds__(64 * VW) k_trinv(LaunchSet ls) {
   const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
   const int B = d.B, Bp = d.Bp, T = Bp / 16;
-  const int b = local / T, j = local % T;
+  const int b = d.fslot0 + local / T, j = local % T;
   if (d.status[b] != 0) return;
   const double* lf = d.lfac + b * d.lf_stride;
   const double* scg = lf + 256 * lf_tiles(T);
@@ -486,7 +488,7 @@ __global__ void __launch_bounds__(256) k_wop(LaunchSet ls) {
   const int bi = find_batch(ls, blockIdx.x, local);
   const BatchDesc& d = ls.d[bi];
   const int B = d.B, Bp = d.Bp, T = Bp / 16;
-  const int b = local / T, t = local % T;
+  const int b = d.fslot0 + local / T, t = local % T;
   if (d.status[b] != 0) return;
   constexpr bool LP = (WP == P_BF16 || WP == P_F16 || WP == P_FP8);
   constexpr int top = (WP == P_FP8) ? 7 : 14;   // scaled row maximum lands in [2^top, 2^(top+1))
@@ -538,9 +540,10 @@ __global__ void __launch_bounds__(256) k_wop(LaunchSet ls) {
 }
 
 // Causal mode 2: slot nblk (the window before the batch, which scores block
-// 0) is the previous batch's last slot, already factored: copy what the
-// whitening reads (mean, operand or FP64 W, band and row scales, status) and
-// count block 0 as the factor counts the blocks it scores.  CPWG workgroups
+// 0, or every block in one-pass mode) is a slot of the previous batch,
+// already factored: copy what the whitening reads (mean, operand or FP64 W,
+// band and row scales, status) and count the blocks it scores as the factor
+// counts them.  CPWG workgroups
 // per batch share the copies in 16-byte strides (every size is a multiple of
 // 16 bytes); the first one also moves the status.
 __global__ void __launch_bounds__(256) k_copy_slot(LaunchSet ls) {
@@ -562,9 +565,11 @@ __global__ void __launch_bounds__(256) k_copy_slot(LaunchSet ls) {
     const int st = d.src_status[0];
     d.status[n] = st;
     d.clipflag[n] = 0;
-    if (causal_empty(d, 0)) atomicAdd(d.nsing + 1, 1u);
-    else if (st == 1) atomicAdd(d.nsing, 1u);
-    else if (st == 2) atomicAdd(d.nsing + 1, 1u);
+    int with, without;
+    slot_scores(d, n, with, without);
+    if (without) atomicAdd(d.nsing + 1, (unsigned)without);
+    if (with && st == 1) atomicAdd(d.nsing, (unsigned)with);
+    else if (with && st == 2) atomicAdd(d.nsing + 1, (unsigned)with);
   }
 }
 

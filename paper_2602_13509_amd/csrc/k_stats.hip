@@ -466,17 +466,9 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
 // the exact raw band sums.  Every wave issues exactly S2IT loads per chunk,
 // also for rounds past the band count, so waiting for a chunk is a fixed
 // count of outstanding loads that the compiler can follow slot by slot.
-typedef __attribute__((ext_vector_type(2))) unsigned short u16x2;
 constexpr int S3ROWS = 16 * MAXT;          // band rows (shift table)
 constexpr int S3RING = 128 * S2IT;         // rows per ring buffer: S2IT rounds of 128
 
-// Workgroup barrier that orders LDS accesses only.  A plain __syncthreads()
-// also waits for every outstanding global access of the wave, which would
-// drain the direct-to-LDS loads queued for later chunks; those are waited for
-// explicitly, chunk by chunk, before the barrier that publishes them.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
 
 // R > 1 (launches with few splits, e.g. a lone block): R workgroups share a
 // split, all staging every chunk of it; workgroup r of the R multiplies only

@@ -196,14 +196,7 @@ constexpr int W2_FREE_CUS = 32;                // CUs the tile kernel leaves to 
 constexpr int W2G = 4;                        // 16-pixel products per tile
 constexpr int W2TP = 16 * W2G;                // pixels per tile
 constexpr int MAXS = (MAXT + 1) / 2;          // 32-band operand steps
-constexpr int MAXFR = (MAXT / 2) * (MAXT / 2 + 1) + ((MAXT & 1) ? (MAXT / 2 + 1) : 0);
-
-// Operand fragments before out-band tile i: sum over m = 1..i of ceil(m / 2)
-// (tile i spans the in-band steps 0..i/2 of the lower triangle).
-__host__ __device__ constexpr int fr_off(int i) {
-  return (i / 2) * (i / 2 + 1) + ((i & 1) ? (i / 2 + 1) : 0);
-}
-static_assert(fr_off(MAXT) == MAXFR, "fragment count");
+constexpr int MAXFR = fr_off(MAXT);
 
 template <int P> __device__ __forceinline__ typename MM<P>::frag pack_frag(const typename MM<P>::storage e[8]);
 template <> __device__ __forceinline__ bf16x8 pack_frag<P_BF16>(const uint16_t e[8]) {

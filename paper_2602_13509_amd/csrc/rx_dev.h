@@ -122,6 +122,7 @@ template <> __device__ __forceinline__ uint8_t to_storage<P_FP8>(float v) { retu
 typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(2))) _Float16 f16x2;
+typedef __attribute__((ext_vector_type(2))) unsigned short u16x2;
 template <int P> __device__ __forceinline__ uint32_t cvt_pack2(float a, float b);
 template <> __device__ __forceinline__ uint32_t cvt_pack2<P_BF16>(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
@@ -268,6 +269,11 @@ struct BatchDesc {
                           // slot nblk holds the window before the batch): 1 = slot nblk is
                           // formed by the merge and factored here, 2 = it is copied from the
                           // previous batch's last slot (the src_* pointers) by k_copy_slot
+  int onepass;            // causal mode, every block scored with slot nblk (the window before the push)
+  int lag_empty;          // one-pass: a window started earlier in the push (every block scores NaN)
+  int fslot0;             // first factored snapshot slot (one-pass: only the last, and slot nblk
+                          // when it is formed here, score anything)
+  uint8_t wrow[16][2];     // one-pass kernel: out-band tiles each wave whitens (0xff: none)
   const double* src_mu; const void* src_wlp; const double* src_w64;
   const float* src_isc; const float* src_osc; const int* src_status;
   int64_t wl_bytes;       // whitening operand bytes per slot (0 on the FP64 path)
@@ -325,14 +331,47 @@ __device__ __forceinline__ int find_batch(const LaunchSet& ls, int wg, int& loca
 __device__ __forceinline__ int blk_lines_of(const BatchDesc& d, int b) {
   return b == d.nblk - 1 ? d.last_lines : d.blk_lines;
 }
-// Snapshot slot whose statistics score block b: the window after block b
-// (update, then score), or in causal mode the window before it.
-__device__ __forceinline__ int snap_slot(const BatchDesc& d, int b) {
-  return d.causal ? (b == 0 ? d.nblk : b - 1) : b;
+// Whitening operand in matrix-core fragment order: fragments before out-band
+// tile i, the sum over m = 1..i of ceil(m / 2) (tile i spans the 32-band
+// in-band steps 0..i/2 of the lower triangle).
+__host__ __device__ constexpr int fr_off(int i) {
+  return (i / 2) * (i / 2 + 1) + ((i & 1) ? (i / 2 + 1) : 0);
 }
-// Causal mode: a block that starts a new window has no statistics before it.
+
+// Workgroup barrier that orders LDS accesses only.  A plain __syncthreads()
+// also waits for every outstanding global access of the wave, which would
+// drain the direct-to-LDS loads queued for later chunks; those are waited for
+// explicitly, chunk by chunk, before the barrier that publishes them.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Snapshot slot whose statistics score block b: the window after block b
+// (update, then score), in causal mode the window before it, in one-pass
+// mode the window before the push (slot nblk for every block).
+__device__ __forceinline__ int snap_slot(const BatchDesc& d, int b) {
+  return d.causal ? ((b == 0 || d.onepass) ? d.nblk : b - 1) : b;
+}
+// Causal mode: a block that starts a new window has no statistics before it;
+// one-pass mode: neither has a block after such a start within the push.
 __device__ __forceinline__ bool causal_empty(const BatchDesc& d, int b) {
-  return d.causal && ((d.reset_bits >> b) & 1ull);
+  if (!d.causal) return false;
+  if (d.onepass) return d.lag_empty || (d.reset_bits & (b >= 63 ? ~0ull : ((2ull << b) - 1ull))) != 0;
+  return (d.reset_bits >> b) & 1ull;
+}
+// Blocks of the batch that snapshot slot s scores, split into those with
+// statistics (counted as singular / not ready by the slot's status) and
+// those without (not ready whatever the slot holds).
+__device__ __forceinline__ void slot_scores(const BatchDesc& d, int s, int& nwith, int& nwithout) {
+  nwith = nwithout = 0;
+  if (!d.causal) { nwith = 1; return; }
+  if (d.onepass) {
+    if (s != d.nblk) return;
+    for (int b = 0; b < d.nblk; ++b) (causal_empty(d, b) ? nwithout : nwith) += 1;
+    return;
+  }
+  const int b = s == d.nblk ? 0 : (s + 1 < d.nblk ? s + 1 : -1);
+  if (b >= 0) (causal_empty(d, b) ? nwithout : nwith) = 1;
 }
 __device__ __forceinline__ int ks_of(const BatchDesc& d, int b) {
   return b == d.nblk - 1 ? d.ks_last : d.ks;

@@ -32,6 +32,7 @@ extern "C" hipError_t rxk_launch_stats(int in_type, int prec, int phase, const L
                                        const LaunchSet* ls2, int wg2, hipStream_t st);
 extern "C" hipError_t rxk_launch_factor(int wprec, const LaunchSet* ls, int wg, hipStream_t st);
 extern "C" hipError_t rxk_launch_copy_slot(const LaunchSet* ls, int nb, hipStream_t st);
+extern "C" hipError_t rxk_launch_onepass(const LaunchSet* ls, int wg, int Bw, hipStream_t st);
 extern "C" hipError_t rxk_launch_whiten(int in_type, int wprec, const LaunchSet* ls, int wg, int Bw,
                                         hipStream_t st);
 extern "C" hipError_t rxk_launch_mask(const void* sc, int f64, int64_t n, int mode, double tau, int64_t k,
@@ -168,6 +169,46 @@ static int splits_for(int64_t lines, int cpl, int sp) {
 // Rectangles of at most 4 x 4 16-band tiles covering the lower triangle of
 // T x T tiles (bands of 4 tile rows cut into 4-column pieces: at most 15
 // for T <= 20), assigned to waves so the four SIMDs of a CU get similar work.
+// One-pass kernel: the out-band whitening tiles each of its 16 waves takes
+// (at most two), so that the four SIMDs (wave w on SIMD w % 4) get similar
+// matrix-core work once the covariance super-tiles are counted: wave w owns
+// lower super-tile w (row-major) and multiplies 4 fragments per stored
+// fragment row of it; whitening tile i takes i / 2 + 1 steps for each of
+// the two 16-sample groups.  Heaviest tiles first, each to the least loaded
+// SIMD, then its least loaded wave with a free place.
+static void make_wrows(int T, uint8_t wrow[16][2]) {
+  int wl[16], sl[4] = {0, 0, 0, 0}, cnt[16];
+  const int nsr = (T + 3) / 4;
+  for (int w = 0; w < 16; ++w) {
+    int I = 0, t = w;
+    while (t > I) { t -= I + 1; ++I; }
+    const int J = t;
+    int rows = 0;
+    if (I < nsr)
+      for (int ii = 0; ii < 4; ++ii) {
+        bool any = false;
+        for (int j = 0; j < 4; ++j)
+          any |= 4 * I + ii < T && 4 * J + j < T && (I > J || ii >= j);
+        rows += any;
+      }
+    wl[w] = 4 * rows;
+    sl[w % 4] += wl[w];
+    cnt[w] = 0;
+    wrow[w][0] = wrow[w][1] = 0xff;
+  }
+  for (int i = T - 1; i >= 0; --i) {
+    const int cost = 2 * (i / 2 + 1);
+    int bw = -1;
+    for (int w = 0; w < 16; ++w) {
+      if (cnt[w] == 2) continue;
+      if (bw < 0 || sl[w % 4] < sl[bw % 4] || (sl[w % 4] == sl[bw % 4] && wl[w] < wl[bw])) bw = w;
+    }
+    wrow[bw][cnt[bw]++] = (uint8_t)i;
+    wl[bw] += cost;
+    sl[bw % 4] += cost;
+  }
+}
+
 static int make_rects(int T, uint8_t rect[16][4]) {
   struct Rc { int r0, c0, nr, nc, n; };
   std::vector<Rc> v;
@@ -250,6 +291,11 @@ struct rx_stream {
   rx_config cfg{};
   int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
   int causal = 0;                         // blocks scored with the window before them
+  int onepass = 0;                        // ... before their push (causal is then set too)
+  // one-pass: the window count before the push, and whether a window has
+  // started within the push so far
+  int64_t N_push = 0;
+  bool push_reset = false;
   // causal: the previous batch's last snapshot slot (the window before the
   // next batch, already factored), valid until the statistics are replaced
   // or the snapshot buffers are reallocated
@@ -296,6 +342,7 @@ struct rx_stream {
   // end of the last push that read it
   DevBuf bip;
   hipEvent_t ev_bip = nullptr;
+  hipEvent_t ev_shift = nullptr;          // one-pass kernel: the batch's centring shifts are written
   // host input staging
   DevBuf stage;
   void* host_pin = nullptr;
@@ -409,14 +456,17 @@ static rx_status validate(const rx_config* c) {
   if (c->ddof != 0 && c->ddof != 1) return fail(RX_E_ARG, "ddof must be 0 or 1");
   if (c->block_lines < 0 || c->window_lines < 0) return fail(RX_E_ARG, "block_lines and window_lines must be >= 0");
   if (!(c->ridge_rel >= 0.0) || !std::isfinite(c->ridge_rel)) return fail(RX_E_ARG, "ridge_rel must be finite and >= 0");
-  if ((c->flags & ~RX_FLAG_CAUSAL) != 0) return fail(RX_E_ARG, "unknown flags");
+  if ((c->flags & ~(RX_FLAG_CAUSAL | RX_FLAG_ONE_PASS)) != 0) return fail(RX_E_ARG, "unknown flags");
+  if ((c->flags & RX_FLAG_CAUSAL) && (c->flags & RX_FLAG_ONE_PASS))
+    return fail(RX_E_ARG, "RX_FLAG_CAUSAL and RX_FLAG_ONE_PASS are exclusive");
   if (c->in_type == RX_IN_U16 && (c->bit_depth < 0 || c->bit_depth > 16)) return fail(RX_E_ARG, "bit_depth must be in [0, 16]");
   return RX_OK;
 }
 
 static size_t stream_bytes(const rx_config* c, int max_block_lines) {
   const int Bp = pad16(c->bands);
-  const int slots = 1 + ((c->flags & RX_FLAG_CAUSAL) ? 1 : 0);     // causal: the window before the block
+  // causal and one-pass: the window before the block (push)
+  const int slots = 1 + ((c->flags & (RX_FLAG_CAUSAL | RX_FLAG_ONE_PASS)) ? 1 : 0);
   const Sizes z = scratch_sizes(c->bands, c->samples, c->in_type, c->syrk_prec, slots, std::max(1, max_block_lines));
   const size_t state = 2 * ((size_t)(Bp + 1) * 8 + (size_t)Bp * Bp * 8);
   // the snapshot, factor and validity buffers come in two parity sets
@@ -472,7 +522,7 @@ static void free_stream(rx_stream* s) {
   s->prof_pool.clear();
   s->prof_open.clear();
   hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_merged[0], s->ev_merged[1],
-                      s->ev_fact, s->ev_white[0], s->ev_white[1], s->ev_last, s->ev_bip};
+                      s->ev_fact, s->ev_white[0], s->ev_white[1], s->ev_last, s->ev_bip, s->ev_shift};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
   if (s->own_st) {
@@ -543,7 +593,8 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
   s->Bw = pad32(s->Bp);
   s->S = cfg->samples;
   s->in_type = cfg->in_type;
-  s->causal = (cfg->flags & RX_FLAG_CAUSAL) ? 1 : 0;
+  s->causal = (cfg->flags & (RX_FLAG_CAUSAL | RX_FLAG_ONE_PASS)) ? 1 : 0;
+  s->onepass = (cfg->flags & RX_FLAG_ONE_PASS) ? 1 : 0;
   s->sp = cfg->syrk_prec;
   s->wp = cfg->whiten_prec;
   s->cpl = ceil_div(s->S, KC);
@@ -584,7 +635,8 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
     s->npar = 2;
   }
   hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_merged[0],
-                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last, &s->ev_bip};
+                       &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last, &s->ev_bip,
+                       &s->ev_shift};
   for (hipEvent_t* e : evs)
     if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return bail(fail(RX_E_DEVICE, "hipEventCreate failed"));
   const size_t s1b = (size_t)(s->Bp + 1) * 8, m2b = (size_t)s->Bp * s->Bp * 8;
@@ -659,6 +711,8 @@ struct Job {
   int par;
   int wg_valid, wg_shift, wg_syrk, wg_merge, wg_mmat, wg_factor, wg_whiten;
   int copy = 0;           // causal: slot nblk is copied from the previous batch (k_copy_slot)
+  int fused = 0;          // one-pass: covariance product and scores in one kernel (k_onepass)
+  int wg_fused = 0;
   int fast = 0;           // ... and the whitening waits only for the input (one block, pipelined)
 };
 
@@ -726,6 +780,7 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   int64_t lines = 0;
   for (size_t i = i0; i < i1; ++i) lines += blks[i].lines;
   const int64_t npx = lines * s->S;
+  const bool lag_empty = s->push_reset;     // one-pass: a window started in an earlier batch of the push
   // reserve_batches has sized every buffer and the FIFO for this batch
   if ((size_t)(s->tail + npx) * (s->sc_f64 ? 8 : 4) > s->pend[s->pcur].cap)
     return fail(RX_E_STATE, "internal: batch prepared without a reservation");
@@ -756,11 +811,18 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
       rb |= 1ull << b;
       s->N = 0;
     }
-    if (s->causal && ((s->cfg.ridge_rel == 0.0 && s->N <= s->B) || s->N <= s->cfg.ddof)) notready = true;
+    if (s->onepass) {
+      if (bk.reset) s->push_reset = true;
+      if (s->push_reset || (s->cfg.ridge_rel == 0.0 && s->N_push <= s->B) || s->N_push <= s->cfg.ddof) notready = true;
+    } else if (s->causal && ((s->cfg.ridge_rel == 0.0 && s->N <= s->B) || s->N <= s->cfg.ddof)) {
+      notready = true;
+    }
     s->N += (int64_t)bk.lines * s->S;
     if (!s->causal && s->cfg.ridge_rel == 0.0 && s->N <= s->B) notready = true;
   }
   d.reset_bits = rb;
+  d.onepass = s->onepass;
+  d.lag_empty = s->onepass && lag_empty;
   const int q = s->par;                     // parity set of this batch's buffers
   j.par = q;
   d.shift = static_cast<double*>(s->shift.p);
@@ -806,6 +868,11 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
     d.src_status = static_cast<const int*>(s->status[pp].p) + ps;
   }
   j.copy = copy ? 1 : 0;
+  // one-pass with the window before the push in place: one read of the lines
+  // (16-bit, 16-byte aligned rows with S % 8 == 0, BF16 products, <= 272 bands)
+  j.fused = (copy && s->onepass && s->in_type == RX_IN_U16 && s->sp == RX_BF16 && s->wp == RX_BF16 &&
+             s->Bp <= 272 && d.vec_ok) ? 1 : 0;
+  if (j.fused) make_wrows(s->Bp / 16, d.wrow);
   d.nsing = static_cast<unsigned int*>(s->nsing.p);
   d.cnt64 = reinterpret_cast<unsigned long long*>(static_cast<char*>(s->nsing.p) + 8);
   d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
@@ -822,7 +889,14 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.wg_mmat = 0;                            // merge, matrix part: row strips of 4 x 64 entries
   for (int g = 0; g < s->Bp / 4; ++g) j.wg_mmat += (4 * g + 67) / 64;
   j.wg_factor = nblk + (d.causal == 1 ? 1 : 0);   // causal, slot formed here: also the window before the batch
+  if (s->onepass) {
+    // only the window after the batch (the next batch's window before the
+    // push, or the next push's) and a slot nblk formed here score anything
+    d.fslot0 = nblk - 1;
+    j.wg_factor = 1 + (d.causal == 1 ? 1 : 0);
+  }
   j.wg_whiten = (int)(lines * s->cpl);
+  j.wg_fused = (nblk - 1) * d.ks + d.ks_last;
 
   s->cur ^= 1;
   s->tail += npx;
@@ -833,7 +907,9 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   if (s->causal) {
     s->prev_valid = true;
     s->prev_par = q;
-    s->prev_slot = nblk - 1;
+    // one-pass: a later batch of the same push takes this batch's slot nblk,
+    // the window before the push
+    s->prev_slot = (s->onepass && i1 < blks.size()) ? nblk : nblk - 1;
   }
   return RX_OK;
 }
@@ -967,6 +1043,10 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, 
   // input, not this batch's statistics, so it is queued first (its scores do
   // not wait behind the host time of the statistics launches)
   const bool early = ps && jobs[0].fast;
+  // one-pass kernel: a lone stream's pipelined batch with its window-before
+  // slot copied (it scores the batch as it forms the covariance partials)
+  const bool fused = ps && jobs[0].fused;
+  if (fused && !piped) return fail(RX_E_STATE, "internal: one-pass launch without its queues");
   if (early) {
     if (pe->in_event) HIPC(hipStreamWaitEvent(qs.C, ps->ev_in, 0));
     rx_status r0 = whiten_all();
@@ -991,9 +1071,23 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, 
                              const int n4 = fill(e, grp, g0, g1, &Job::wg_mmat);
                              HIPC(rxk_launch_stats(it, sp, 0, &a, n1, nullptr, 0, qs.A));
                              if ((q = prof_mark(prof, 0, false, qs.A)) != RX_OK) return q;
-                             if ((q = prof_mark(prof, 1, true, qs.A)) != RX_OK) return q;
-                             HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, qs.A));
-                             if ((q = prof_mark(prof, 1, false, qs.A)) != RX_OK) return q;
+                             if (fused) {
+                               // the one-pass kernel runs where the scores are read (queue C),
+                               // after the shifts (queue A) and the window-before copy (queue C)
+                               HIPC(hipEventRecord(ps->ev_shift, qs.A));
+                               HIPC(hipStreamWaitEvent(qs.C, ps->ev_shift, 0));
+                               LaunchSet f;
+                               const int nf = fill(f, grp, g0, g1, &Job::wg_fused);
+                               if ((q = prof_mark(prof, 1, true, qs.C)) != RX_OK) return q;
+                               HIPC(rxk_launch_onepass(&f, nf, jobs[grp[g0]].Bw, qs.C));
+                               if ((q = prof_mark(prof, 1, false, qs.C)) != RX_OK) return q;
+                               // the merge below waits for this event: the partials are written
+                               HIPC(hipEventRecord(pe->ev_white[pe->par], qs.C));
+                             } else {
+                               if ((q = prof_mark(prof, 1, true, qs.A)) != RX_OK) return q;
+                               HIPC(rxk_launch_stats(it, sp, 1, &b, n2, nullptr, 0, qs.A));
+                               if ((q = prof_mark(prof, 1, false, qs.A)) != RX_OK) return q;
+                             }
                              if (piped) HIPC(hipStreamWaitEvent(qs.A, pe->ev_white[pe->par], 0));
                              // causal: the latest whitening (and the copy before it) read
                              // the other parity's last slot, which this merge's successor
@@ -1023,9 +1117,9 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, 
   if (r != RX_OK) return r;
   if (piped) {
     HIPC(hipEventRecord(pe->ev_fact, qs.B));
-    if (!early) HIPC(hipStreamWaitEvent(qs.C, pe->ev_fact, 0));
+    if (!early && !fused) HIPC(hipStreamWaitEvent(qs.C, pe->ev_fact, 0));
   }
-  return early ? RX_OK : whiten_all();
+  return (early || fused) ? RX_OK : whiten_all();
 }
 
 // ---------------------------------------------------------------------------- push
@@ -1110,12 +1204,17 @@ extern "C" rx_status rx_push_lines(rx_stream* s, const void* lines, int64_t n_li
     if (is_device_ptr) HIPC(hipEventRecord(s->ev_in, qs.A));   // the fast causal path waits for the copy
   }
   bool notready = false;
+  s->N_push = s->N;
+  s->push_reset = false;
   for (const auto& bt : batches) {
     const size_t i = bt.first, k = bt.second;
     std::vector<Job> jobs(1);
     if ((r = prepare_job(s, x, blks, i, k, jobs[0], notready, true)) != RX_OK) { s->broken = true; return r; }
     // (float input: the whitening also reads the validity pass's output)
-    jobs[0].fast = jobs[0].copy && k - i == 1 && is_device_ptr && !one_queue && s->in_type == RX_IN_U16;
+    // (one-pass: every block of the batch whitens with the copied slot)
+    jobs[0].fast = jobs[0].copy && (k - i == 1 || s->onepass) && is_device_ptr && !one_queue &&
+                   s->in_type == RX_IN_U16 && !jobs[0].fused;
+    if (one_queue) jobs[0].fused = 0;
     // resident lines need no input event (a BIP push's copy on queue A does)
     const Pipe pe{s->ev_merged, s->ev_fact, s->ev_white, jobs[0].par, s->causal != 0, !resident || bip};
     if ((r = launch_jobs(jobs, qs, &pe, s)) != RX_OK) { s->broken = true; return r; }
@@ -1593,6 +1692,8 @@ static rx_status step_locked(rx_server* srv, int32_t* n_blocks) {
   for (size_t i = 0; i < take.size(); ++i) {
     rx_stream* s = take[i].s;
     bool notready = false;
+    s->N_push = s->N;                      // a served block is a push of its own
+    s->push_reset = false;
     rx_status r = prepare_job(s, take[i].x, blks[i], 0, 1, jobs[i], notready);
     if (r != RX_OK) {
       for (size_t k = 0; k <= i; ++k) take[k].s->broken = true;

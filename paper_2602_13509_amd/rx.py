@@ -22,6 +22,7 @@ RX_LINES_HOST, RX_LINES_DEVICE, RX_LINES_RESIDENT = 0, 1, 2
 RX_FP64, RX_FP32, RX_BF16, RX_FP16, RX_FP8_E4M3 = 0, 1, 2, 3, 4
 RX_THR_ABS, RX_THR_REL_MAX, RX_THR_TOPK = 0, 1, 2
 RX_FLAG_CAUSAL = 1
+RX_FLAG_ONE_PASS = 2
 RX_MAX_BANDS = 320
 RX_MASK_NOALLOC_BYTES = 4096 + (1 << 20)
 RX_MASK_NOALLOC_MAX_PX = 1 << 23
@@ -153,7 +154,7 @@ def _stream_handle(stream) -> int:
 
 def make_config(bands: int, samples: int, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ddof=0,
                 ridge_rel=0.0, block_lines=0, window_lines=0, bit_depth=12, device=0, causal=False,
-                layout=RX_BIL) -> rx_config:
+                layout=RX_BIL, one_pass=False) -> rx_config:
     cfg = rx_config()
     check(LIB.rx_config_init(C.byref(cfg), bands, samples))
     cfg.in_type = IN_TYPE[np.dtype(in_dtype)]
@@ -162,7 +163,7 @@ def make_config(bands: int, samples: int, in_dtype=np.uint16, syrk="bf16", white
     cfg.whiten_prec = PREC[whiten] if isinstance(whiten, str) else whiten
     cfg.ddof, cfg.ridge_rel = ddof, float(ridge_rel)
     cfg.block_lines, cfg.window_lines, cfg.device = block_lines, window_lines, device
-    cfg.flags = RX_FLAG_CAUSAL if causal else 0
+    cfg.flags = (RX_FLAG_CAUSAL if causal else 0) | (RX_FLAG_ONE_PASS if one_pass else 0)
     cfg.layout = layout
     return cfg
 

@@ -51,9 +51,9 @@ def assert_mask(got_mask, ref_scores, tau_eff, tol, bands, label=""):
 
 
 def oracle_stream_scores(cube, bands, samples, block_lines=0, window_lines=0, ddof=0, rho=0.0, pushes=None,
-                         causal=False):
+                         causal=False, one_pass=False):
     o = RxStreamOracle(bands, samples, ddof=ddof, rho=rho, window_lines=window_lines, block_lines=block_lines,
-                       causal=causal)
+                       causal=causal, one_pass=one_pass)
     if pushes is None:
         pushes = [cube.shape[0]]
     out, l0 = [], 0

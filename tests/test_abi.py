@@ -46,7 +46,7 @@ def test_config_defaults_and_host_validation():
     b = C.c_size_t()
     assert rx.LIB.rx_stream_footprint(C.byref(cfg), 100, C.byref(b)) == rx.RX_OK and b.value > 0
     for field, bad in (("bands", 0), ("bands", 321), ("samples", 0), ("syrk_prec", 5),
-                       ("whiten_prec", 9), ("ddof", 2), ("layout", 2), ("flags", 2), ("struct_size", 4)):
+                       ("whiten_prec", 9), ("ddof", 2), ("layout", 2), ("flags", 4), ("struct_size", 4)):
         c2 = rx.rx_config()
         C.memmove(C.byref(c2), C.byref(cfg), C.sizeof(cfg))
         setattr(c2, field, bad)
@@ -83,3 +83,20 @@ def test_footprint_accounts_for_causal_slot_and_float_validity():
     assert rx.make_config(16, 16, causal=True).flags == rx.RX_FLAG_CAUSAL
     names = [f[0] for f in rx.rx_counters._fields_]
     assert names[-3:] == ["nonfinite_px", "fp8_saturated", "fp8_syrk_saturated"]
+
+
+def test_one_pass_flag_is_exclusive_with_causal_and_takes_the_extra_slot():
+    # Host logic only: the one-pass flag keeps the window-before slot (same
+    # footprint as causal mode) and cannot be combined with the causal flag;
+    # unknown flag bits are refused.
+    import numpy as np
+    from paper_2602_13509_amd import rx
+    assert rx.make_config(16, 16, one_pass=True).flags == rx.RX_FLAG_ONE_PASS
+    causal = rx.stream_footprint(rx.make_config(270, 640, in_dtype=np.uint16, causal=True), 100)
+    one = rx.stream_footprint(rx.make_config(270, 640, in_dtype=np.uint16, one_pass=True), 100)
+    assert one == causal
+    for flags in (rx.RX_FLAG_CAUSAL | rx.RX_FLAG_ONE_PASS, 4):
+        cfg = rx.make_config(16, 16)
+        cfg.flags = flags
+        n = C.c_size_t()
+        assert rx.LIB.rx_stream_footprint(C.byref(cfg), 16, C.byref(n)) == rx.RX_E_ARG
