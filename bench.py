@@ -88,7 +88,7 @@ def roofline(kernel, w, ms):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_sensor_2000x640x270.md")
 KERNEL_SOURCES = {"covariance": "k_stats.hip", "merge": "k_stats.hip", "factor": "k_factor.hip",
-                  "whiten_score": "k_whiten.hip"}
+                  "whiten_score": "k_whiten.hip", "onepass": "k_onepass.hip"}
 
 
 def measured_traffic(phase):
@@ -137,10 +137,12 @@ def measured_hbm_gbs(torch, mib=1024, reps=10):
     return 2.0 * (mib << 20) / float(np.median(times)) / 1e9
 
 
-def run_path(rx, torch, x, prec, steps, warmup, label, repeats=0):
+def run_path(rx, torch, x, prec, steps, warmup, label, repeats=0, one_pass=False):
+    # one-pass scoring takes a cumulative window: a 2000-line window would
+    # restart with every push, leaving no window before it to score with
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
                          ridge_rel=RIDGE if prec in ("bf16", "fp16", "fp8") else 0.0, block_lines=BLOCK,
-                         window_lines=LINES)
+                         window_lines=0 if one_pass else LINES, one_pass=one_pass)
     st = rx.RxStream(cfg)
     npx = LINES * SAMPLES
     sc = torch.empty(npx, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
@@ -298,12 +300,12 @@ def host_input(rx, torch, cube, steps=3):
             "bytes_per_step": int(cube.nbytes)}
 
 
-def latency(rx, torch, x, prec, nblocks, causal=False):
+def latency(rx, torch, x, prec, nblocks, causal=False, one_pass=False):
     """Push of one 100-line block (device input, GPU idle) to its scores in
     the caller's device buffer: the time until the caller's stream has them
     (statistics work the scores do not depend on may still be running)."""
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
-                         ridge_rel=RIDGE, block_lines=0, window_lines=LINES, causal=causal)
+                         ridge_rel=RIDGE, block_lines=0, window_lines=LINES, causal=causal, one_pass=one_pass)
     st = rx.RxStream(cfg)
     sc = torch.empty(BLOCK * SAMPLES, dtype=torch.float32, device="cuda")
     lat = []
@@ -322,14 +324,14 @@ def latency(rx, torch, x, prec, nblocks, causal=False):
     return float(np.median(lat)), float(np.quantile(lat, 0.99))
 
 
-def one_block_pushes(rx, torch, x, prec, steps=10, warmup=2):
+def one_block_pushes(rx, torch, x, prec, steps=10, warmup=2, one_pass=False):
     """The cube delivered the way a push-broom sensor delivers it: twenty
     consecutive pushes of one 100-line block each (device input, no host
     synchronisation between them), each followed by the pop of that block's
     scores into a device buffer.  Returns pixel-spectra/s over steps cubes."""
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk=prec, whiten=prec,
                          ridge_rel=RIDGE if prec in ("bf16", "fp16", "fp8") else 0.0, block_lines=0,
-                         window_lines=LINES)
+                         window_lines=LINES, one_pass=one_pass)
     st = rx.RxStream(cfg)
     sc = torch.empty(BLOCK * SAMPLES, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
     blocks = [x[b * BLOCK:(b + 1) * BLOCK] for b in range(LINES // BLOCK)]
@@ -581,6 +583,36 @@ def serving(rx, torch, seconds, replay_all_at_once, budget=64 << 30, compress=1.
                            "max": float(lat.max())}}
 
 
+def one_pass_leg(rx, torch, x, steps, warmup, hbm_meas=None):
+    """One-pass scoring of the same resident cube (every push scored with the
+    window before it, cumulative window): one push of 20 blocks per step;
+    from the second push on, the single-read kernel forms the covariance
+    partials and the scores, and only the window after the push is factored.
+    Its launch time (phase 1 of the profiled pass) against one read of the
+    lines and one write of the scores, and the two products' matrix-core
+    work: 2 B(B+1) + 2B flop per pixel (lower-triangle covariance and
+    triangular whitening, squares and sums)."""
+    t, ms, n, _, spread = run_path(rx, torch, x, "bf16", steps, warmup, "one-pass bf16", repeats=5, one_pass=True)
+    npx = LINES * SAMPLES
+    per = [ms[i] / max(n[i], 1) for i in range(5)]
+    k_ms = per[1]
+    by = npx * (BANDS * 2 + 4)
+    fl = npx * (2 * BANDS * (BANDS + 1) + 2 * BANDS)
+    sec = k_ms * 1e-3
+    roof = {"kernel": "k_onepass", "bound": "hbm", "achieved": by / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": by / sec / 1e9 / HBM_PEAK_GBS, "mfma_frac": fl / sec / 1e12 / PEAK_TFLOPS["bf16"],
+            "algorithmic_bytes": by, "algorithmic_flops": fl, "avg_launch_ms": k_ms,
+            "traffic": measured_traffic("onepass")}
+    if hbm_meas:
+        roof["frac_measured"] = roof["achieved"] / hbm_meas
+    obp = one_block_pushes(rx, torch, x, "bf16", one_pass=True)
+    l50, l99 = latency(rx, torch, x, "bf16", 200, one_pass=True)
+    return {"value": npx / t, "ms_per_step": t * 1e3, "steps": steps, "value_repeats": spread,
+            "phase_ms": dict(zip(PHASES, per)), "roofline": roof, "one_block_pushes": obp,
+            "latency_ms": {"block_lines": BLOCK, "p50": l50, "p99": l99, "samples": 200},
+            "config": "same cube, RX_FLAG_ONE_PASS, cumulative window, 20 blocks of 100 lines per push"}
+
+
 def cpu_baseline(cube, budget_s):
     """The FP64 oracle as it stands, on the first blocks of the same cube, for
     about budget_s seconds of CPU time (at least one block).  When a whole
@@ -659,6 +691,8 @@ def main():
         obp = one_block_pushes(rx, torch, x, "bf16", steps=3, warmup=1)
         p50, p99 = latency(rx, torch, x, "bf16", 20)
         log(f"profile run: one-block pushes {obp['px_per_s']:.4e} px/s; block latency p50 {p50:.3f} ms")
+        t_op, _, _, _, _ = run_path(rx, torch, x, "bf16", args.steps, 3, "one-pass bf16", one_pass=True)
+        log(f"profile run: one-pass {LINES * SAMPLES / t_op:.4e} px/s")
         if args.copy_mib > 0:
             src = torch.empty(args.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
             dst = torch.empty_like(src)
@@ -722,6 +756,12 @@ def main():
 
     hbm_meas = measured_hbm_gbs(torch)
     log(f"measured HBM bandwidth (1 GiB device copy): {hbm_meas:.0f} GB/s")
+    op = one_pass_leg(rx, torch, x, args.steps, args.warmup, hbm_meas)
+    log(f"one-pass scoring: {op['value']:.4e} px/s, {op['ms_per_step']:.3f} ms/step; single-read kernel "
+        f"{op['roofline']['avg_launch_ms']:.4f} ms = {op['roofline']['achieved']:.0f} GB/s "
+        f"({op['roofline']['frac']:.3f} of spec, {op['roofline'].get('frac_measured', 0):.3f} of measured), "
+        f"MFMA {op['roofline']['mfma_frac']:.3f}; one-block pushes {op['one_block_pushes']['px_per_s']:.4e} px/s; "
+        f"block latency p50 {op['latency_ms']['p50']:.3f} ms, p99 {op['latency_ms']['p99']:.3f} ms")
 
     # the counter runs' reference: this copy must stay the program's last one
     if args.copy_mib > 0:
@@ -803,6 +843,7 @@ def main():
         "one_block_pushes": obp,
         "latency_ms": {"block_lines": BLOCK, "p50": p50, "p99": p99, "samples": 200},
         "latency_ms_causal": {"block_lines": BLOCK, "p50": c50, "p99": c99, "samples": 200},
+        "one_pass": op,
         "score_error_vs_oracle": {"max_rel": float(err.max()), "p99_rel": float(np.quantile(err, 0.99)),
                                   "pixels": int(nref)},
         "precision": prec_rep,

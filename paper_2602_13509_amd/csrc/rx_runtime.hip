@@ -166,9 +166,6 @@ static int splits_for(int64_t lines, int cpl, int sp) {
   return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (nch + per - 1) / per));
 }
 
-// Rectangles of at most 4 x 4 16-band tiles covering the lower triangle of
-// T x T tiles (bands of 4 tile rows cut into 4-column pieces: at most 15
-// for T <= 20), assigned to waves so the four SIMDs of a CU get similar work.
 // One-pass kernel: the out-band whitening tiles each of its 16 waves takes
 // (at most two), so that the four SIMDs (wave w on SIMD w % 4) get similar
 // matrix-core work once the covariance super-tiles are counted: wave w owns
@@ -209,6 +206,9 @@ static void make_wrows(int T, uint8_t wrow[16][2]) {
   }
 }
 
+// Rectangles of at most 4 x 4 16-band tiles covering the lower triangle of
+// T x T tiles (bands of 4 tile rows cut into 4-column pieces: at most 15
+// for T <= 20), assigned to waves so the four SIMDs of a CU get similar work.
 static int make_rects(int T, uint8_t rect[16][4]) {
   struct Rc { int r0, c0, nr, nc, n; };
   std::vector<Rc> v;

@@ -75,6 +75,43 @@ def test_sensor_cube_full_size_sampled(rxm, sensor_full):
     assert_scores(got["bf16"][idx], np.concatenate(refbf), B, 5e-2, 1e-2, "sensor full bf16")
 
 
+def test_sensor_cube_full_size_one_pass_sampled(rxm, sensor_full):
+    # One-pass scoring at full size in the launch configuration the benchmark
+    # times (blocks of 100 lines, cumulative window): lines 0-999 as one
+    # push (nothing before it: NaN), then lines 1000-1999 as one push, which
+    # the single-read kernel scores with the window of the first thousand
+    # lines while forming its covariance partials.  Sampled scores against
+    # the oracle (exact integer moments of lines 0-999, LU solve, same ridge)
+    # at the BF16 tolerance; the statistics of all 2000 lines against the
+    # exact integer covariance (the BF16 covariance bound of the stats test).
+    import torch
+    L, S, B, BL = 2000, 640, 270, 100
+    cube = sensor_full
+    x = torch.from_numpy(cube).cuda()
+    st = rxm.RxStream(rxm.make_config(B, S, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=1e-6,
+                                      block_lines=BL, window_lines=0, one_pass=True))
+    assert st.rx_push_lines(x[:1000]) == rxm.RX_E_NOTREADY
+    assert st.rx_push_lines(x[1000:]) == rxm.RX_OK
+    st.rx_sync()
+    got = st.scores_host()
+    n, mean, cov = st.rx_get_stats()
+    st.rx_destroy()
+    assert np.isnan(got[:1000 * S]).all()
+    mu1, cov1 = orx.stats(orx.pixels(cube[:1000]))
+    px2 = orx.pixels(cube[1000:])
+    rng = np.random.default_rng(6)
+    pick = np.sort(rng.choice(px2.shape[0], 8000, replace=False))
+    ref = orx.scores(px2[pick], mu1, orx.regularise(cov1, 1e-6))
+    say(f"sensor full size one-pass: {pick.size} sampled pixels of the second push")
+    assert_scores(got[1000 * S + pick], ref, B, 5e-2, 1e-2, "sensor full one-pass bf16")
+    mu, cv = orx.stats(orx.pixels(cube))
+    assert n == L * S
+    assert np.max(np.abs(mean - mu)) <= 1e-12 * np.abs(mu).max()
+    err = np.max(np.abs(cov - cv)) / np.abs(cv).max()
+    say(f"  one-pass statistics of 2000 lines: max |cov err| / max|cov| = {err:.3e}")
+    assert err <= 2e-2
+
+
 def test_sensor_cube_full_size_bf16_masks(rxm, sensor_full):
     # Mask agreement of the BF16 path (BF16 covariance and whitening, FP64
     # factor, 1e-6 ridge) with the FP64 oracle (same ridge) over every pixel
