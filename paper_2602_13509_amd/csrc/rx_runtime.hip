@@ -166,6 +166,19 @@ static int splits_for(int64_t lines, int cpl, int sp) {
   return (int)std::min<int64_t>(cap, std::max<int64_t>(1, (nch + per - 1) / per));
 }
 
+// One-pass kernel: its covariance splits for a batch of nblk
+// blocks, the block of `lines` lines having ks for the covariance kernels:
+// at least ks, and enough that the launch holds one workgroup per CU, at
+// most kMaxSplits and one 32-sample chunk per split.  Its 32-bit raw sums
+// take at most 8191 chunks a split; 0 when no count satisfies both.
+static int onepass_splits(int ks, int64_t lines, int S, int nblk, int ncu) {
+  const int64_t nch = lines * ceil_div(S, 32);
+  int64_t k = std::max<int64_t>(ks, ncu / std::max(1, nblk));
+  k = std::min<int64_t>(std::min<int64_t>(k, kMaxSplits), nch);
+  k = std::max<int64_t>(k, (nch + 8190) / 8191);
+  return k > kMaxSplits ? 0 : (int)k;
+}
+
 // One-pass kernel: the out-band whitening tiles each of its 16 waves takes
 // (at most two), so that the four SIMDs (wave w on SIMD w % 4) get similar
 // matrix-core work once the covariance super-tiles are counted: wave w owns
@@ -256,10 +269,10 @@ static int64_t lf_stride_for(int Bp) {
   return 256 * (T + T * (T - 1) / 2) + Bp;
 }
 
-static Sizes scratch_sizes(int B, int S, int in_type, int sp, int nblk, int blk_lines) {
+static Sizes scratch_sizes(int B, int S, int in_type, int sp, int nblk, int blk_lines, int ks_min = 0) {
   const int Bp = pad16(B), Bw = pad32(Bp);
   const int nsr = ceil_div(Bp, SUP), nsup = nsr * (nsr + 1) / 2;
-  const int ks = splits_for(blk_lines, ceil_div(S, KC), sp);
+  const int ks = std::max(ks_min, splits_for(blk_lines, ceil_div(S, KC), sp));
   const size_t psz = sp == RX_FP64 ? 8 : 4;
   Sizes z;
   z.shift = (size_t)nblk * Bp * 8;
@@ -292,6 +305,7 @@ struct rx_stream {
   int B = 0, Bp = 0, Bw = 0, S = 0, in_type = 0, sp = 0, wp = 0, cpl = 0;
   int causal = 0;                         // blocks scored with the window before them
   int onepass = 0;                        // ... before their push (causal is then set too)
+  int ncu = 0;                            // compute units of the device
   // one-pass: the window count before the push, and whether a window has
   // started within the push so far
   int64_t N_push = 0;
@@ -533,8 +547,8 @@ static void free_stream(rx_stream* s) {
   s->magic = 0;
 }
 
-static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines) {
-  const Sizes z = scratch_sizes(s->B, s->S, s->in_type, s->sp, nblk, blk_lines);
+static rx_status alloc_scratch(rx_stream* s, int nblk, int blk_lines, int ks_min = 0) {
+  const Sizes z = scratch_sizes(s->B, s->S, s->in_type, s->sp, nblk, blk_lines, ks_min);
   rx_status r;
   if ((r = dev_ensure(s->shift, z.shift, s)) != RX_OK) return r;
   if ((r = dev_ensure(s->part, z.part, s)) != RX_OK) return r;
@@ -601,6 +615,10 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
   s->esz = in_elem_size(s->in_type);
   s->dev = cfg->device;
   s->sc_f64 = s->wp == RX_FP64 ? 1 : 0;
+  if (hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->dev) != hipSuccess || s->ncu < 1) {
+    (void)hipGetLastError();
+    s->ncu = 1;
+  }
 
   auto bail = [&](rx_status st) {
     std::string keep = g_err;
@@ -748,6 +766,13 @@ static std::vector<std::pair<size_t, size_t>> plan_batches(const std::vector<Blo
   return out;
 }
 
+// One-pass kernel: the configurations it covers (the input pointer must also
+// give 16-byte aligned rows).
+static bool onepass_kernel_config(const rx_stream* s) {
+  return s->onepass && s->in_type == RX_IN_U16 && s->sp == RX_BF16 && s->wp == RX_BF16 && s->Bp <= 272 &&
+         ((size_t)s->S * s->esz) % 16 == 0;
+}
+
 // Everything the batches of a push (or of a server step) can allocate,
 // reserved before any stream state changes: scratch for each batch (buffers
 // only grow, so the largest need wins) and FIFO room for all their pixels.
@@ -760,7 +785,11 @@ static rx_status reserve_batches(rx_stream* s, const std::vector<Block>& blks,
   for (int i = 0; i < 6; ++i) cap0[i] = kept[i]->cap;
   int64_t lines = 0;
   for (const auto& bt : batches) {
-    rx_status r = alloc_scratch(s, (int)(bt.second - bt.first) + s->causal, blks[bt.first].lines);
+    const int nb = (int)(bt.second - bt.first);
+    int ks_min = 0;
+    if (onepass_kernel_config(s))
+      ks_min = onepass_splits(splits_for(blks[bt.first].lines, s->cpl, s->sp), blks[bt.first].lines, s->S, nb, s->ncu);
+    rx_status r = alloc_scratch(s, nb + s->causal, blks[bt.first].lines, ks_min);
     if (r != RX_OK) return r;
     for (size_t i = bt.first; i < bt.second; ++i) lines += blks[i].lines;
   }
@@ -870,9 +899,17 @@ static rx_status prepare_job(rx_stream* s, const void* x, const std::vector<Bloc
   j.copy = copy ? 1 : 0;
   // one-pass with the window before the push in place: one read of the lines
   // (16-bit, 16-byte aligned rows with S % 8 == 0, BF16 products, <= 272 bands)
-  j.fused = (copy && s->onepass && s->in_type == RX_IN_U16 && s->sp == RX_BF16 && s->wp == RX_BF16 &&
-             s->Bp <= 272 && d.vec_ok) ? 1 : 0;
-  if (j.fused) make_wrows(s->Bp / 16, d.wrow);
+  j.fused = (copy && onepass_kernel_config(s) && d.vec_ok) ? 1 : 0;
+  if (j.fused) {
+    const int ks = onepass_splits(d.ks, L, s->S, nblk, s->ncu), ksl = onepass_splits(d.ks_last, last, s->S, nblk, s->ncu);
+    if (ks > 0 && ksl > 0) {
+      d.ks = ks;
+      d.ks_last = ksl;
+      make_wrows(s->Bp / 16, d.wrow);
+    } else {
+      j.fused = 0;
+    }
+  }
   d.nsing = static_cast<unsigned int*>(s->nsing.p);
   d.cnt64 = reinterpret_cast<unsigned long long*>(static_cast<char*>(s->nsing.p) + 8);
   d.scores = static_cast<char*>(s->pend[s->pcur].p) + (size_t)s->tail * (s->sc_f64 ? 8 : 4);
