@@ -126,8 +126,10 @@ typedef struct rx_config {
  * whitening products then reads every line once: one kernel stages each
  * chunk of lines, whitens and scores it with the window before the push and
  * adds it to the covariance product (Section "System Implementation /
- * Detection Algorithm", Eq. 1).  Other configurations take the same scores
- * from the two-pass kernels.  Not with RX_FLAG_CAUSAL. */
+ * Detection Algorithm", Eq. 1).  Other configurations, a push whose window
+ * before it is formed in the push (the first push, after rx_set_stats) and
+ * served streams (each submitted block is a push of its own) take the same
+ * scores from the two-pass kernels.  Not with RX_FLAG_CAUSAL. */
 #define RX_FLAG_ONE_PASS 2
 
 typedef struct rx_counters {
