@@ -320,3 +320,66 @@ def test_request_loop_mix_equals_alone_bitwise(rxm):
         assert np.array_equal(got.view(np.uint32), alone[k].view(np.uint32)), f"stream {k} (B={B}, S={S})"
         st.rx_destroy()
     srv.rx_server_destroy()
+
+
+def test_served_one_pass_streams(rxm):
+    # One-pass scoring on the server: every submitted block is a push of its
+    # own, scored with the window before it (its slot formed in the step and
+    # factored there).  The FP64 stream scores bit for bit as the same
+    # stream alone pushing the same blocks (whose window-before slot is
+    # copied from the previous push) and matches the oracle's one-pass mode;
+    # the BF16 stream matches the oracle within the BF16 bounds (scaled by
+    # sqrt(270 / B) below 270 bands); an update-then-score stream shares the
+    # launches.
+    import torch
+    rng = np.random.default_rng(13)
+    specs = []   # (B, S, prec, one_pass, blocks, cube)
+    for B, S, prec, op in [(96, 200, "fp64", True), (120, 320, "bf16", True), (64, 256, "fp64", False)]:
+        blocks = [int(v) for v in rng.integers(8, 25, size=5)]
+        cube = synth.sensor_cube(300 + B, lines=sum(blocks), samples=S, bands=B).cube
+        specs.append((B, S, prec, op, blocks, cube))
+
+    def cfg(B, S, prec, op, bl):
+        return rxm.make_config(B, S, in_dtype=np.uint16, syrk=prec, whiten=prec,
+                               ridge_rel=1e-6 if prec == "bf16" else 0.0, block_lines=bl, one_pass=op)
+
+    dcubes = [dev(s[5]) for s in specs]
+    alone = []
+    for (B, S, prec, op, blocks, cube), dc in zip(specs, dcubes):
+        st = rxm.RxStream(cfg(B, S, prec, op, 0))
+        l0 = 0
+        for n in blocks:
+            st.rx_push_lines(dc[l0:l0 + n])
+            l0 += n
+        st.rx_sync()
+        alone.append(st.scores_host(f64=(prec == "fp64")))
+        st.rx_destroy()
+    srv = rxm.RxServer(8 << 30, 16)
+    served = [rxm.RxStream(cfg(B, S, prec, op, 64), server=srv) for (B, S, prec, op, _, _) in specs]
+    order = [(i, j) for i, s in enumerate(specs) for j in range(len(s[4]))]
+    rng.shuffle(order)
+    nxt = [0] * len(specs)
+    starts = [np.concatenate([[0], np.cumsum(s[4])]) for s in specs]
+    tag = 0
+    for i, _ in order:
+        j = nxt[i]
+        nxt[i] += 1
+        srv.rx_server_submit(served[i], dcubes[i][int(starts[i][j]):int(starts[i][j + 1])], tag)
+        tag += 1
+    while srv.rx_server_queued()[0] > 0:
+        srv.rx_server_step()
+    assert sorted(srv.rx_server_poll(block=True)) == list(range(tag))
+    torch.cuda.synchronize()
+    for k, ((B, S, prec, op, blocks, cube), st) in enumerate(zip(specs, served)):
+        got = st.scores_host(f64=(prec == "fp64"))
+        rho = 1e-6 if prec == "bf16" else 0.0
+        ref, o = oracle_stream_scores(cube, B, S, rho=rho, pushes=blocks, one_pass=op)
+        assert st.rx_get_counters().notready_blocks == o.status.count("notready")
+        if prec == "fp64":
+            assert np.array_equal(got.view(np.uint64), alone[k].view(np.uint64)), f"stream {k} (B={B}, one_pass={op})"
+            assert_scores(got, ref, B, 1e-9, 1e-11, label=f"served B={B} one_pass={op}")
+        else:
+            f = max(1.0, (270.0 / B) ** 0.5)
+            assert_scores(got, ref, B, 5e-2 * f, 1e-2 * f, label=f"served B={B} one_pass={op} bf16")
+        st.rx_destroy()
+    srv.rx_server_destroy()
