@@ -71,3 +71,23 @@ def test_bip_refused_for_served_streams(rxm):
         rxm.RxStream(rxm.make_config(16, 32, layout=rxm.RX_BIP), server=srv)
     assert e.value.status == rxm.RX_E_ARG
     srv.rx_server_destroy()
+
+
+@pytest.mark.parametrize("device", [True, False])
+def test_bip_one_pass_equals_bil_bitwise(rxm, device):
+    # One-pass scoring with BF16 products: from the second push on the
+    # single-read kernel runs, on the transposed BIL copy (BIP) or on the
+    # staged host lines; the scores and statistics equal those of device BIL
+    # pushes bit for bit, and match the oracle's one-pass mode.
+    B, S, L = 72, 96, 40
+    cube = synth.sensor_cube(57, lines=L, samples=S, bands=B).cube
+    pushes = [8, 12, 20]
+    say(f"one-pass BIP / host input, device={device}")
+    a = _run(rxm, cube, rxm.RX_BIL, "bf16", True, pushes, block_lines=4, one_pass=True)
+    b = _run(rxm, cube, rxm.RX_BIP, "bf16", device, pushes, block_lines=4, one_pass=True)
+    c = _run(rxm, cube, rxm.RX_BIL, "bf16", device, pushes, block_lines=4, one_pass=True)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=4, rho=1e-6, pushes=pushes, one_pass=True)
+    f = (270.0 / B) ** 0.5
+    assert_scores(a, ref, B, 5e-2 * f, 1e-2 * f, label="one-pass bf16 BIL")
