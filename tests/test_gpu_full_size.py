@@ -171,8 +171,7 @@ def test_stress_cube_full_size_sampled(rxm):
         if w != "fp64":
             wmat = st.rx_get_whitener()
             n2, mean, cov2 = st.rx_get_stats()
-            emu, scale = emulate_scores(px, mean, cov2, wmat, w, with_scale=True)
-            bound = 2.0 * 1024 * 2.0 ** -24 * scale + 1e-6 * np.maximum(emu, 1e-3 * B)
+            emu, bound = emulate_scores(px, mean, cov2, wmat, w, with_bound=True)
             e = np.abs(out[w] - emu)
             mx, p99 = err_summary(out[w], ref, B)
             c = st.rx_get_counters()
