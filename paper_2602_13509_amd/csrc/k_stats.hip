@@ -291,8 +291,9 @@ __global__ void __launch_bounds__(S2NT) k_syrk2(LaunchSet ls) {
   const T* xb = static_cast<const T*>(d.x) + (int64_t)b * d.blk_lines * d.B * d.S;
 
   // staging items: item = row * 8 + segment of 8 samples, fixed per thread.
-  // Raw sums are exact: uint32 for 16-bit input (at most 80 chunks x 8 values
-  // x 65535 per thread), FP64 otherwise.
+  // Raw sums are exact: uint32 for 16-bit input (a split has at most 8192
+  // chunks, and a thread adds 8 values of at most 65535 per chunk to each
+  // sum: below 2^32), FP64 otherwise.
   using RS = typename std::conditional<IN == IN_U16, uint32_t, double>::type;
   float shf[S2IT], bsc[S2IT];               // shift, and the FP8 operand's band scale
   RS rawsum[S2IT];
