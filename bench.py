@@ -278,8 +278,9 @@ def paper_workload(rx, torch, reps=5):
 
 def host_input(rx, torch, cube, steps=3):
     """The same mixed-path step with the cube pushed from host memory: the
-    library copies it into its pinned buffer and then to the device, so
-    this rate includes both copies (PCIe-inclusive; never the headline)."""
+    library copies it in chunks into its pinned buffers and from there to the
+    device, so this rate includes both copies (PCIe-inclusive; never the
+    headline)."""
     cfg = rx.make_config(BANDS, SAMPLES, in_dtype=np.uint16, syrk="bf16", whiten="bf16", ridge_rel=RIDGE,
                          block_lines=BLOCK, window_lines=LINES)
     st = rx.RxStream(cfg)

@@ -167,7 +167,10 @@ rx_status rx_init(const rx_config* cfg, rx_server* server, rx_stream** out);
 /* Push n_lines >= 1 lines, BIL [n_lines][B][S] (or BIP [n_lines][S][B] with
  * cfg->layout = RX_BIP) of cfg->in_type, contiguous.
  * is_device_ptr = RX_LINES_HOST (0): lines is host memory, copied before the
- * call returns (the caller may reuse it at once).  RX_LINES_DEVICE (1):
+ * call returns (the caller may reuse it at once): up to eight threads copy
+ * it in 8 MiB chunks into the stream's pinned buffers (two per thread, 16
+ * MiB each thread), and each chunk's transfer to the device overlaps the
+ * copies of later chunks.  RX_LINES_DEVICE (1):
  * lines is device memory on cfg->device, read asynchronously after the work
  * already queued on hip_stream; it must stay unchanged until rx_sync returns
  * or hip_stream passes an rx_wait on this stream.  RX_LINES_RESIDENT (2):

@@ -323,7 +323,7 @@ struct rx_stream {
   // served streams run everything on the server's single queue.
   hipStream_t st = nullptr, stA = nullptr, stB = nullptr;
   bool own_st = false;
-  hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr, ev_hcopy = nullptr;
+  hipEvent_t ev_in = nullptr, ev_done = nullptr, ev_stage = nullptr;
   hipEvent_t ev_fact = nullptr, ev_merged[2] = {nullptr, nullptr}, ev_white[2] = {nullptr, nullptr};
   // end of the latest push (recorded on st): a push finding it complete runs
   // on st alone; after such a push, the next pipelined one makes stA wait for it
@@ -357,10 +357,15 @@ struct rx_stream {
   DevBuf bip;
   hipEvent_t ev_bip = nullptr;
   hipEvent_t ev_shift = nullptr;          // one-pass kernel: the batch's centring shifts are written
-  // host input staging
+  // host input staging: pinned chunk buffers, two per copy thread (see
+  // stage_host_input), and the device copy of the push's lines
+  struct HostSlot {
+    void* p = nullptr;
+    hipEvent_t ev = nullptr;      // the slot's latest host-to-device copy
+    bool busy = false;
+  };
+  std::vector<HostSlot> hslots;
   DevBuf stage;
-  void* host_pin = nullptr;
-  size_t host_pin_cap = 0;
   bool stage_busy = false;
   // masks and conversions
   DevBuf maskbits, maskscr, cvt;
@@ -529,13 +534,16 @@ static void free_stream(rx_stream* s) {
                     &s->isc[1], &s->osc[0], &s->osc[1], &s->status[0], &s->status[1], &s->evb, &s->dvb, &s->coefb,
                     &s->nbvb, &s->valid[0], &s->valid[1], &s->lfac[0], &s->lfac[1], &s->nbadl, &s->bip, &s->sscale, &s->nsing, &s->pend[0], &s->pend[1], &s->stage, &s->maskbits, &s->maskscr, &s->cvt};
   for (DevBuf* b : bufs) dev_free(*b);
-  if (s->host_pin) (void)hipHostFree(s->host_pin);
-  s->host_pin = nullptr;
+  for (auto& hs : s->hslots) {
+    if (hs.p) (void)hipHostFree(hs.p);
+    if (hs.ev) (void)hipEventDestroy(hs.ev);
+  }
+  s->hslots.clear();
   for (auto& pe : s->prof_open) { s->prof_pool.push_back(pe.second.first); s->prof_pool.push_back(pe.second.second); }
   for (hipEvent_t e : s->prof_pool) (void)hipEventDestroy(e);
   s->prof_pool.clear();
   s->prof_open.clear();
-  hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_hcopy, s->ev_merged[0], s->ev_merged[1],
+  hipEvent_t evs[] = {s->ev_in, s->ev_done, s->ev_stage, s->ev_merged[0], s->ev_merged[1],
                       s->ev_fact, s->ev_white[0], s->ev_white[1], s->ev_last, s->ev_bip, s->ev_shift};
   for (hipEvent_t e : evs)
     if (e) (void)hipEventDestroy(e);
@@ -652,7 +660,7 @@ extern "C" rx_status rx_init(const rx_config* cfg, rx_server* srv, rx_stream** o
       return bail(fail(RX_E_DEVICE, "hipStreamCreate failed"));
     s->npar = 2;
   }
-  hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_hcopy, &s->ev_merged[0],
+  hipEvent_t* evs[] = {&s->ev_in, &s->ev_done, &s->ev_stage, &s->ev_merged[0],
                        &s->ev_merged[1], &s->ev_fact, &s->ev_white[0], &s->ev_white[1], &s->ev_last, &s->ev_bip,
                        &s->ev_shift};
   for (hipEvent_t* e : evs)
@@ -1160,31 +1168,66 @@ static rx_status launch_jobs(std::vector<Job>& jobs, Queues qs, const Pipe* pe, 
 }
 
 // ---------------------------------------------------------------------------- push
-// Host lines go through one pinned buffer and one device staging buffer:
-// the pinned buffer is refilled once the previous copy out of it is done
-// (ev_hcopy, host wait); the staging buffer is overwritten on queue A only
-// after the previous push's whitening, the last reader, is done (ev_stage).
+// Host lines reach the device staging buffer in chunks of kHostChunk bytes:
+// up to kHostThreads threads (the calling one and helpers started for the
+// push) each take every T-th chunk, copy it into one of their two pinned
+// buffers and queue its host-to-device copy on queue A, so the host copies
+// of later chunks overlap the transfers of earlier ones.  A pinned buffer is
+// refilled once its previous transfer is done (its event, a host wait);
+// the staging buffer is overwritten on queue A only after the previous
+// push's whitening, its last reader, is done (ev_stage).
+static constexpr size_t kHostChunk = size_t(8) << 20;
+static constexpr int kHostThreads = 8;
+
 static rx_status stage_host_input(rx_stream* s, const void* lines, size_t bytes, const void** x) {
   if (s->stage_busy) {
-    HIPC(hipEventSynchronize(s->ev_hcopy));
     HIPC(hipStreamWaitEvent(s->stA, s->ev_stage, 0));
     s->stage_busy = false;
   }
-  if (bytes > s->host_pin_cap) {
-    if (s->host_pin) HIPC(hipHostFree(s->host_pin));
-    s->host_pin = nullptr;
-    s->host_pin_cap = 0;
-    if (hipHostMalloc(&s->host_pin, bytes, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(RX_E_NOMEM, "hipHostMalloc(%zu) failed", bytes);
-    }
-    s->host_pin_cap = bytes;
-  }
   rx_status r = dev_ensure(s->stage, bytes, s);
   if (r != RX_OK) return r;
-  std::memcpy(s->host_pin, lines, bytes);
-  HIPC(hipMemcpyAsync(s->stage.p, s->host_pin, bytes, hipMemcpyHostToDevice, s->stA));
-  HIPC(hipEventRecord(s->ev_hcopy, s->stA));
+  const size_t nch = (bytes + kHostChunk - 1) / kHostChunk;
+  const int T = (int)std::min<size_t>(kHostThreads, nch);
+  while ((int)s->hslots.size() < 2 * T) {
+    rx_stream::HostSlot hs;
+    if (hipHostMalloc(&hs.p, kHostChunk, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RX_E_NOMEM, "hipHostMalloc(%zu) failed", kHostChunk);
+    }
+    if (hipEventCreateWithFlags(&hs.ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipHostFree(hs.p);
+      return fail(RX_E_DEVICE, "hipEventCreate failed");
+    }
+    s->hslots.push_back(hs);
+  }
+  // worker w copies chunks w, w + T, ... through its slots 2w and 2w + 1
+  std::vector<hipError_t> err(T, hipSuccess);
+  auto work = [&](int w) {
+    hipError_t e = hipSetDevice(s->dev);
+    int k = 0;
+    for (size_t c = w; e == hipSuccess && c < nch; c += T, ++k) {
+      rx_stream::HostSlot& hs = s->hslots[2 * w + (k & 1)];
+      if (hs.busy && (e = hipEventSynchronize(hs.ev)) != hipSuccess) break;
+      hs.busy = false;
+      const size_t off = c * kHostChunk, len = std::min(kHostChunk, bytes - off);
+      std::memcpy(hs.p, static_cast<const char*>(lines) + off, len);
+      e = hipMemcpyAsync(static_cast<char*>(s->stage.p) + off, hs.p, len, hipMemcpyHostToDevice, s->stA);
+      if (e == hipSuccess) e = hipEventRecord(hs.ev, s->stA);
+      hs.busy = e == hipSuccess;
+    }
+    err[w] = e;
+  };
+  std::vector<std::thread> helpers;
+  try {
+    for (int w = 1; w < T; ++w) helpers.emplace_back(work, w);
+  } catch (...) {
+    for (auto& t : helpers) t.join();
+    return fail(RX_E_STATE, "could not start the host copy threads");
+  }
+  work(0);
+  for (auto& t : helpers) t.join();
+  for (int w = 0; w < T; ++w)
+    if (err[w] != hipSuccess) return fail(RX_E_DEVICE, "host input copy: %s", hipGetErrorString(err[w]));
   s->stage_busy = true;
   *x = s->stage.p;
   return RX_OK;

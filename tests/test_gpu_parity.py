@@ -140,6 +140,29 @@ def test_sensor_cube_host_input_and_push_split(rxm):
     assert_scores(st.scores_host(f64=True), ref, B, *TOL["fp64"], label="host input, pushes 7/13/40")
 
 
+def test_large_host_pushes_equal_device_pushes(rxm):
+    # Host pushes of several 8 MiB copy chunks (three and five copy threads,
+    # a ragged last chunk, chunk edges inside lines), back to back so that the
+    # second push refills pinned buffers whose transfers are queued: the
+    # scores and statistics equal those of the same lines pushed from device
+    # memory, bit for bit.
+    B, S = 270, 256
+    cube = synth.sensor_cube(16, lines=400, samples=S, bands=B).cube
+    pushes = [150, 250]
+    say(f"large host pushes: {pushes} lines of {S}x{B} u16 ({cube.nbytes >> 20} MiB)")
+    kw = dict(block_lines=50, ridge_rel=1e-6)
+    a = run_stream(rxm, cube, "bf16", "bf16", pushes=pushes, device_input=False, **kw)
+    b = run_stream(rxm, cube, "bf16", "bf16", pushes=pushes, device_input=True, **kw)
+    got = a.scores_host()                     # pops the scores
+    assert np.array_equal(got.view(np.uint32), b.scores_host().view(np.uint32))
+    sa, sb = a.rx_get_stats(), b.rx_get_stats()
+    assert sa[0] == sb[0] and np.array_equal(sa[1], sb[1]) and np.array_equal(sa[2], sb[2])
+    ref, _ = oracle_stream_scores(cube, B, S, block_lines=50, rho=1e-6, pushes=pushes)
+    assert_scores(got, ref, B, *TOL["bf16"], label="large host pushes")
+    a.rx_destroy()
+    b.rx_destroy()
+
+
 def test_window_reset_matches_independent_cubes(rxm):
     B, S = 64, 80
     cube = synth.sensor_cube(13, lines=75, samples=S, bands=B).cube
